@@ -1,0 +1,188 @@
+/*
+ * fjofc.h — C ABI of the MI355X (gfx950) fast-JOFC library.
+ *
+ * Fast JOFC (Lyzinski, Park, Priebe, Trosset: "Fast Embedding for JOFC
+ * Using the Raw Stress Criterion") embeds m matched n x n dissimilarity
+ * matrices Delta_1..Delta_m in R^d by minimising the JOFC raw stress
+ * (eq. stress) with successive Guttman transforms, applying the
+ * pseudo-inverse of the omnibus Laplacian through its exact structured
+ * form (Section 2.1 and Appendix A: L^dagger = W^-1 (x) I_n + Z (x) J_n,
+ * whose J_n part drops out because 1^T B(X) = 0), so that one transform is
+ *     X_t^(j) = sum_l [W^-1]_{jl} B_l(X^(l)) X^(l)        (eq:update)
+ * with W the m x m matrix of eq:modW.  Out-of-sample embedding of new
+ * objects against a fixed configuration (Section 3) is the second entry
+ * point.
+ *
+ * Conventions for every call:
+ *  - Integer return codes (FJOFC_OK = 0); nothing is thrown across the ABI.
+ *    fjofc_last_error() gives a message for the calling thread's last
+ *    failure.
+ *  - "device" pointers are HIP device memory on the context's device,
+ *    owned by the caller; the library never frees them.  "host" pointers
+ *    are ordinary host memory.
+ *  - All GPU work is enqueued on `stream` (a hipStream_t, NULL = default
+ *    stream).  Calls that return host results synchronise that stream
+ *    before returning.
+ *  - Weights: `wmat` is the m x m FP64 row-major matrix of eq:W2:
+ *    wmat[i*m+i] = w_ii > 0 is modality i's fidelity weight (Theorem 1
+ *    needs w_ii > 0); wmat[i*m+k] = w_ik = w_ki >= 0 is the
+ *    commensurability weight between modalities i and k.  The uniform case
+ *    of eq:W is w_ii = 1, w_ik = w.  Arbitrary mn x mn weights are not
+ *    accepted: the structured inverse needs the eq:W2 structure.
+ *  - Dissimilarities are FP32, n x n row-major, symmetric with zero
+ *    diagonal (the library reads only the strict upper triangle j < l).
+ *  - Configurations are FP32 row-major: X is (m*n) x d, modality-major
+ *    (rows i*n .. i*n+n-1 hold X^(i), Section 1.2.1).
+ */
+#ifndef FJOFC_H
+#define FJOFC_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    FJOFC_OK = 0,
+    FJOFC_EINVAL = 1,   /* invalid argument (shape, weight, pointer)       */
+    FJOFC_EHIP = 2,     /* a HIP runtime call failed                       */
+    FJOFC_ENOMEM = 3,   /* device or host allocation failed                */
+    FJOFC_ESINGULAR = 4 /* the eq:modW matrix is singular                   */
+};
+
+/* Stop-rule modes of fjofc_embed (Algorithm 2's loop; the printed loop test
+ * has its sign reversed — the run continues while stress keeps decreasing):
+ * every `stress_every` transforms the raw stress sigma(X_t) is compared with
+ * the previous checkpoint's sigma_prev and the run stops, returning X_t,
+ * when sigma_prev - sigma(X_t) < threshold.                                */
+enum {
+    FJOFC_TOL_NONE = 0, /* run exactly `iters` transforms                  */
+    FJOFC_TOL_REL = 1,  /* threshold = tol * sigma_prev                    */
+    FJOFC_TOL_PAPER = 2 /* threshold = tol * C(mn, 2): the normalised
+                           stress sigma / C(mn,2) failed to decrease by
+                           tol (the paper's experiments use tol = 1e-6)    */
+};
+
+#define FJOFC_MAX_M 32  /* modalities per problem                        */
+#define FJOFC_MAX_D 8   /* embedding dimension                           */
+
+typedef struct fjofc_ctx fjofc_ctx;
+
+typedef struct {
+    int iters_run;       /* Guttman transforms applied to X0              */
+    int converged;       /* 1 if the stop rule fired                      */
+    double stress;       /* raw stress sigma of the returned X (FP64)     */
+    double stress_norm;  /* sigma / C(mn, 2)                               */
+    double fidelity;     /* sum_i w_ii sum_{j<l} (Delta_i[j,l] - d_jl)^2   */
+    double commens;      /* sum_{i<k} w_ik sum_l ||X^(i)_l - X^(k)_l||^2   */
+} fjofc_result;
+
+/* Create a context bound to HIP device `device` (it owns the workspace,
+ * kernel-tile tables and error state).  *out receives the handle.         */
+int fjofc_create(fjofc_ctx **out, int device);
+void fjofc_destroy(fjofc_ctx *ctx);
+
+/* Thread-local message of the last failing call ("" if none).            */
+const char *fjofc_last_error(void);
+const char *fjofc_strerror(int code);
+
+/*
+ * In-sample fJOFC (Algorithm 2 from a given start; Sections 2.1-2.3).
+ *   delta        host array of m device pointers, each an n x n FP32
+ *                dissimilarity Delta_i (row-major, symmetric, zero diag).
+ *   m, n, d      1 <= m <= FJOFC_MAX_M, n >= 2, 1 <= d <= FJOFC_MAX_D.
+ *   wmat         host m x m FP64 eq:W2 weights (see conventions).
+ *   X            device (m*n) x d FP32: X0 on entry, the returned X_t on
+ *                exit.
+ *   iters        maximum number of Guttman transforms (>= 0).
+ *   tol,tol_mode stop rule (FJOFC_TOL_*); ignored when tol <= 0.
+ *   stress_every stress is evaluated at t = 0, every stress_every
+ *                transforms, and for the returned X (>= 1).
+ *   stress_hist  optional host array of iters+1 doubles: sigma(X_t) where
+ *                evaluated, NaN elsewhere.
+ *   res          host result (required).
+ * Each transform streams every Delta_i once (strict upper triangle only),
+ * forming B_i(X^(i)) X^(i) from the pairwise distances (eq:B, with the
+ * d_jl = 0 => 0 rule), then applies W^-1 (eq:update).  Returns after the
+ * stream has been synchronised.                                           */
+int fjofc_embed(fjofc_ctx *ctx, const float *const *delta, int m, int n,
+                const double *wmat, int d, float *X, int iters, double tol,
+                int tol_mode, int stress_every, double *stress_hist,
+                fjofc_result *res, void *stream);
+
+/* Uniform-weight form of fjofc_embed (eq:W: w_ii = 1, w_ik = w >= 0).     */
+int fjofc_embed_w(fjofc_ctx *ctx, const float *const *delta, int m, int n,
+                  double w, int d, float *X, int iters, double tol,
+                  int tol_mode, int stress_every, double *stress_hist,
+                  fjofc_result *res, void *stream);
+
+/* Raw stress (eq. stress, eq:W2 weights) of a configuration X (device,
+ * (m*n) x d), without changing it.  res->iters_run = 0.                   */
+int fjofc_stress(fjofc_ctx *ctx, const float *const *delta, int m, int n,
+                 const double *wmat, int d, const float *X,
+                 fjofc_result *res, void *stream);
+
+/*
+ * Out-of-sample embedding (Section 3) of k new objects against a fixed
+ * in-sample configuration.
+ *   X_in       device (m*n) x d FP32 in-sample configuration (fixed).
+ *   wmat       host m x m eq:W2 weights (as for fjofc_embed).
+ *   delta_new  device k x m x n FP32: delta_new[(o*m + i)*n + j] is the
+ *              dissimilarity of new object o to in-sample object j in
+ *              modality i.
+ *   Y          device k x m x d FP32: starts on entry (the paper starts
+ *              from a random point), results on exit.  Object o's m points
+ *              are rows o*m .. o*m+m-1.
+ *   iters      maximum Guttman transforms per object.
+ *   tol        per object, stop when its out-of-sample stress (eq:joos)
+ *              decreased by less than tol * previous (tol <= 0: never).
+ *   target     optional device k FP64: stop object o once its stress is
+ *              <= target[o] (checked before every transform).
+ *   stress_out optional device k FP64: eq:joos stress of the returned y.
+ *   iters_out  optional device k int32: transforms applied per object.
+ * New objects carry no weight between one another (their mutual
+ * dissimilarities are unknown), so the k problems are independent and
+ * share L22 = the eq:modW matrix (its inverse is the printed L22^dagger
+ * for uniform weights).  Each transform is, per object and modality i,
+ *   r_j = delta_i(j) / ||X^(i)_j - y_i|| (0 when the distance is 0),
+ *   xi_i = w_ii sum_j (1 - r_j) X^(i)_j,  psi_i = w_ii sum_j r_j,
+ *   y <- L22^-1 (xi + diag(psi) y).
+ * The call does not synchronise the stream unless `sync` is non-zero.     */
+int fjofc_oos(fjofc_ctx *ctx, const float *X_in, int m, int n, int d,
+              const double *wmat, const float *delta_new, int k, float *Y,
+              int iters, double tol, const double *target, double *stress_out,
+              int *iters_out, int sync, void *stream);
+
+/*
+ * Per-kernel timing (tracing aid).  While enabled, every kernel launch of
+ * fjofc_embed / fjofc_stress / fjofc_oos is bracketed by HIP events on the
+ * caller's stream; fjofc_profile_read synchronises and returns the summed
+ * durations per kernel kind together with the algorithmic bytes the
+ * in-sample stream launches read (4 bytes per unordered pair of every
+ * dissimilarity block, i.e. one read of each strict-upper-triangle entry)
+ * and that the out-of-sample launches read (4 bytes per
+ * object x modality x in-sample object x transform).  Enabling resets the
+ * counters.
+ */
+typedef struct {
+    int stream_launches;     /* in-sample stream, interior tiles           */
+    double stream_ms;
+    double stream_bytes;
+    int edge_launches;       /* in-sample stream, diagonal / ragged tiles  */
+    double edge_ms;
+    double edge_bytes;
+    int finalize_launches;   /* W^-1 combine and new X                     */
+    double finalize_ms;
+    int reduce_launches;     /* FP64 stress reduction and stop test        */
+    double reduce_ms;
+    int oos_launches;        /* out-of-sample kernel                       */
+    double oos_ms;
+    double oos_bytes;
+} fjofc_profile;
+
+int fjofc_profile_enable(fjofc_ctx *ctx, int on);
+int fjofc_profile_read(fjofc_ctx *ctx, fjofc_profile *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FJOFC_H */

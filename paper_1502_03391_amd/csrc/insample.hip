@@ -1,0 +1,638 @@
+// In-sample fast-JOFC kernels for gfx950.
+//
+// One Guttman transform (Section 2.2, eq:update) is
+//     X_t^(a) = sum_b [W^-1]_{ab} B_b(X^(b)) X^(b)
+// where B_b(X) X has row j equal to sum_{l != j} r_jl (X_j - X_l) with
+// r_jl = w_bb Delta_b[j,l] / d_jl and r_jl = 0 when d_jl = 0 (eq:B).
+//
+// Delta_b is symmetric, so every unordered pair {j,l} is read once, from the
+// strict upper triangle: the pair's term t = r_jl (X_l - X_j) is added to the
+// column accumulator of l and subtracted from the row accumulator of j.  The
+// triangle is cut into th x tw tiles (tw = 64 lanes x CPL columns); one
+// wavefront streams one tile, walking its rows G at a time.  Each lane owns
+// CPL columns of the tile (coalesced 16-byte loads of each row), keeps their
+// column sums in registers for the whole tile, and keeps per-row partial
+// sums for the current G rows; those are reduced across the 64 lanes (a
+// reduce-scatter with permlane swaps and DPP, so each lane finishes one row
+// component) before the next G rows.  The configuration is held in SoA form
+// [m][D][npad] so a group's row points are wave-uniform scalar loads and the
+// column points are vector loads.  Tiles crossing the diagonal or the
+// ragged edge run in a separate masked instance so the interior instance
+// carries no per-element tests.
+//
+// Row and column sums of each tile go to a partial buffer (one slot per
+// tile row / tile column), which the finalize kernel reduces in a fixed
+// order (so results are bitwise reproducible), applies w_bb and W^-1 in
+// FP64, and writes X_{t+1}.  The fidelity term of the raw stress
+// (Remark faststress: it needs only the within-modality distances) is
+// accumulated in the same stream when due: FP32 per lane and group, FP64
+// per lane across groups, one FP64 value per tile.
+#include "fjofc_internal.h"
+#include <float.h>
+
+namespace fjofc {
+namespace {
+
+__device__ __forceinline__ float shfl_xor_f(float v, int mask) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    return __int_as_float(
+        __builtin_amdgcn_ds_bpermute((lane ^ mask) << 2, __float_as_int(v)));
+}
+
+__device__ __forceinline__ double shfl_xor_d(double v, int mask) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    int2 p = *reinterpret_cast<int2 *>(&v);
+    p.x = __builtin_amdgcn_ds_bpermute((lane ^ mask) << 2, p.x);
+    p.y = __builtin_amdgcn_ds_bpermute((lane ^ mask) << 2, p.y);
+    return *reinterpret_cast<double *>(&p);
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) v += shfl_xor_d(v, s);
+    return v;
+}
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+// The configuration is never written while a stream kernel runs; reading it
+// through the constant address space lets wave-uniform reads (a group's row
+// points) compile to scalar loads.
+typedef const __attribute__((address_space(4))) float cfloat;
+
+// DPP controls (gfx9 encoding)
+constexpr int DPP_QP_XOR1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int DPP_QP_XOR2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int DPP_ROW_HALF_MIRROR = 0x141;
+constexpr int DPP_ROW_MIRROR = 0x140;
+constexpr int DPP_ROW_ROR8 = 0x128;
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// Swap halves: returns the sum that lanes 0-31 keep for `a` and lanes 32-63
+// keep for `b` (each summed over the two 32-lane halves).
+__device__ __forceinline__ float swap32_add(float a, float b) {
+    auto s = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(s[0]) + __uint_as_float(s[1]);
+}
+// Same on 16-lane rows: even rows keep `a`, odd rows keep `b`, each summed
+// over the row pair.
+__device__ __forceinline__ float swap16_add(float a, float b) {
+    auto s = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(s[0]) + __uint_as_float(s[1]);
+}
+
+// Column of the tile owned by `lane` for its q-th column (q < CPL).
+// 16-byte path: runs of four consecutive columns, one run per 256 columns;
+// otherwise one column per 64-lane stride.  Both give coalesced row reads.
+template <bool VEC4>
+__device__ __forceinline__ int lane_col(int lane, int q) {
+    return VEC4 ? (q >> 2) * 256 + lane * 4 + (q & 3) : lane + WAVE * q;
+}
+
+// Reduce the G rows' partial sums p[G][D] over the 64 lanes and store each
+// row component from one lane.  Lane bit 5 and bit 4 are reduce-scattered
+// with permlane swaps (each halves the rows a lane holds); for G = 8 lane
+// bit 3 is scattered with a DPP rotate; the remaining low lane bits are
+// summed fully with DPP.  Each lane then holds one row's D sums and stores
+// the component selected by its low lane bits.
+template <int D, int G>
+__device__ __forceinline__ void reduce_rows_store(float (&p)[G][D], int lane,
+                                                  float *prow, int npad,
+                                                  int j0, int nvalid) {
+    constexpr int H1 = G / 2, H2 = G / 4;
+    float a[H1][D];
+#pragma unroll
+    for (int r = 0; r < H1; ++r)
+#pragma unroll
+        for (int k = 0; k < D; ++k) a[r][k] = swap32_add(p[r][k], p[r + H1][k]);
+    float b[H2][D];
+#pragma unroll
+    for (int r = 0; r < H2; ++r)
+#pragma unroll
+        for (int k = 0; k < D; ++k) b[r][k] = swap16_add(a[r][k], a[r + H2][k]);
+    float c[D];
+    int row, kk;
+    if constexpr (G == 8) {
+        const bool b3 = lane & 8;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const float send = b3 ? b[0][k] : b[1][k];
+            const float keep = b3 ? b[1][k] : b[0][k];
+            c[k] = keep + dpp<DPP_ROW_ROR8>(send);
+        }
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            c[k] += dpp<DPP_QP_XOR1>(c[k]);
+            c[k] += dpp<DPP_QP_XOR2>(c[k]);
+            c[k] += dpp<DPP_ROW_HALF_MIRROR>(c[k]);
+        }
+        row = ((lane >> 5) & 1) * 4 + ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1);
+        kk = lane & 7;
+    } else {
+        static_assert(G == 4, "G is 4 or 8");
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            c[k] = b[0][k];
+            c[k] += dpp<DPP_QP_XOR1>(c[k]);
+            c[k] += dpp<DPP_QP_XOR2>(c[k]);
+            c[k] += dpp<DPP_ROW_HALF_MIRROR>(c[k]);
+            c[k] += dpp<DPP_ROW_MIRROR>(c[k]);
+        }
+        row = ((lane >> 5) & 1) * 2 + ((lane >> 4) & 1);
+        kk = lane & 15;
+    }
+    float v = c[0];
+#pragma unroll
+    for (int k = 1; k < D; ++k)
+        if (kk == k) v = c[k];
+    if (kk < D && row < nvalid) prow[(size_t)kk * npad + j0 + row] = v;
+}
+
+template <int CPL, int G, bool VEC4, bool MASK>
+__device__ __forceinline__ void load_rows(float (&dv)[G][CPL],
+                                          const float *__restrict__ dl,
+                                          int n, int j0, int c0, int lane,
+                                          int nvalid) {
+#pragma unroll
+    for (int rr = 0; rr < G; ++rr) {
+        const float *row = dl + (size_t)(j0 + rr) * n + c0;
+        if (VEC4) {
+#pragma unroll
+            for (int h = 0; h < CPL / 4; ++h) {
+                const int c = h * 256 + lane * 4;
+                if (!MASK || (rr < nvalid && c0 + c < n)) {
+                    const f4v v = __builtin_nontemporal_load(
+                        reinterpret_cast<const f4v *>(row + c));
+                    dv[rr][4 * h + 0] = v.x;
+                    dv[rr][4 * h + 1] = v.y;
+                    dv[rr][4 * h + 2] = v.z;
+                    dv[rr][4 * h + 3] = v.w;
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) dv[rr][4 * h + q] = 0.f;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < CPL; ++q) {
+                const int c = lane_col<false>(lane, q);
+                dv[rr][q] = (!MASK || (rr < nvalid && c0 + c < n))
+                                ? __builtin_nontemporal_load(row + c) : 0.f;
+            }
+        }
+    }
+}
+
+// Terms of G rows (given in dv) against the lane's CPL columns.
+template <int D, int CPL, int G, bool VEC4, bool MASK, bool STRESS, bool ACC>
+__device__ __forceinline__ void process_group(
+    const float (&dv)[G][CPL], const float *__restrict__ X, int n, int npad,
+    int r0, int c0, int g0, int nr, int lane, const float (&xc)[CPL][D],
+    float (&cacc)[CPL][D], float *prow, double &fid) {
+    const int nv = MASK ? min(G, nr - g0) : G;
+    // the group's row points (wave-uniform scalar loads; padding rows are 0)
+    float xr[G][D];
+    cfloat *Xc = (cfloat *)X;
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int rr = 0; rr < G; ++rr) xr[rr][k] = Xc[(size_t)k * npad + r0 + g0 + rr];
+    float p[G][D];
+#pragma unroll
+    for (int rr = 0; rr < G; ++rr)
+#pragma unroll
+        for (int k = 0; k < D; ++k) p[rr][k] = 0.f;
+    float fs = 0.f;
+#pragma unroll
+    for (int rr = 0; rr < G; ++rr) {
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) {
+            float diff[D];
+#pragma unroll
+            for (int k = 0; k < D; ++k) diff[k] = xc[q][k] - xr[rr][k];
+            // Starting the squared distance at FLT_MIN keeps the reciprocal
+            // finite for coincident points, whose diff is 0, so eq:B's
+            // d = 0 => 0 rule holds with no extra test.
+            float d2 = fmaf(diff[0], diff[0], FLT_MIN);
+#pragma unroll
+            for (int k = 1; k < D; ++k) d2 = fmaf(diff[k], diff[k], d2);
+            const float rs = __builtin_amdgcn_rsqf(d2);
+            float r = dv[rr][q] * rs;
+            bool ok = true;
+            if (MASK) {
+                const int col = c0 + lane_col<VEC4>(lane, q);
+                const int row = r0 + g0 + rr;
+                ok = (col < n) && (row < n) && (col > row);
+                r = ok ? r : 0.f;
+            }
+            if (ACC) {
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    cacc[q][k] = fmaf(r, diff[k], cacc[q][k]);
+                    p[rr][k] = fmaf(r, diff[k], p[rr][k]);
+                }
+            }
+            if (STRESS) {
+                const float e = dv[rr][q] - d2 * rs;
+                fs = ok ? fmaf(e, e, fs) : fs;
+            }
+        }
+        // Materialise the column sums row by row: otherwise the compiler
+        // sinks their updates to the end of the group and keeps every
+        // row's differences alive until then.
+        if (ACC) {
+#pragma unroll
+            for (int q = 0; q < CPL; ++q)
+#pragma unroll
+                for (int k = 0; k < D; ++k) asm volatile("" : "+v"(cacc[q][k]));
+        }
+        if (STRESS) asm volatile("" : "+v"(fs));
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (ACC) reduce_rows_store<D, G>(p, lane, prow, npad, r0 + g0, nv);
+    if (STRESS) fid += (double)fs;
+}
+
+// One wavefront streams one tile of the strict upper triangle.  MASK is set
+// for boundary tiles: those crossing the diagonal (only l > j counts) or
+// the ragged edge (rows or columns >= n).
+template <int D, int CPL, bool VEC4, bool MASK, bool STRESS, bool ACC>
+__global__ __launch_bounds__(WAVE) void bx_kernel(
+    TriGeom g, DeltaPtrs dp, const float *__restrict__ Xs,
+    const uint32_t *__restrict__ tiles, int tile_off, int ntl,
+    float *__restrict__ P, double *__restrict__ F,
+    const EmbedState *__restrict__ st) {
+    constexpr int G = (CPL == 4) ? 8 : 4;
+    if (st->done) return;
+    const int lane = threadIdx.x;
+    const int w = blockIdx.x;
+    const int i = w / ntl;
+    const int tix = w - i * ntl;
+    const uint32_t tt = tiles[tile_off + tix];
+    const int I = tt >> 16, J = tt & 0xffff;
+    const int n = g.n, npad = g.npad;
+    const int S = g.ntc + g.ntr;
+    const float *__restrict__ dl = dp.p[i];
+    const float *__restrict__ X = Xs + (size_t)i * D * npad;
+    const int c0 = J * g.tw, r0 = I * g.th;
+    const int nr = MASK ? min(g.th, n - r0) : g.th;
+
+    float xc[CPL][D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const float *xk = X + (size_t)k * npad + c0;
+        if (VEC4) {
+#pragma unroll
+            for (int h = 0; h < CPL / 4; ++h) {
+                const float4 v = *reinterpret_cast<const float4 *>(xk + h * 256 + lane * 4);
+                xc[4 * h + 0][k] = v.x;
+                xc[4 * h + 1][k] = v.y;
+                xc[4 * h + 2][k] = v.z;
+                xc[4 * h + 3][k] = v.w;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < CPL; ++q) xc[q][k] = xk[lane_col<false>(lane, q)];
+        }
+    }
+    float cacc[CPL][D];
+#pragma unroll
+    for (int q = 0; q < CPL; ++q)
+#pragma unroll
+        for (int k = 0; k < D; ++k) cacc[q][k] = 0.f;
+    double fid = 0.0;
+    float *Pm = P + (size_t)i * S * D * npad;
+    float *prow = Pm + (size_t)J * D * npad;
+
+    // Two row buffers used alternately (no register copies, so the loads of
+    // the next group stay in flight while the current group is computed).
+    float da[G][CPL], db[G][CPL];
+    load_rows<CPL, G, VEC4, MASK>(da, dl, n, r0, c0, lane, nr);
+    for (int g0 = 0; g0 < nr; g0 += 2 * G) {
+        if (g0 + G < nr)
+            load_rows<CPL, G, VEC4, MASK>(db, dl, n, r0 + g0 + G, c0, lane, nr - g0 - G);
+        process_group<D, CPL, G, VEC4, MASK, STRESS, ACC>(da, X, n, npad, r0, c0, g0, nr,
+                                                          lane, xc, cacc, prow, fid);
+        if (g0 + G >= nr) break;
+        if (g0 + 2 * G < nr)
+            load_rows<CPL, G, VEC4, MASK>(da, dl, n, r0 + g0 + 2 * G, c0, lane,
+                                          nr - g0 - 2 * G);
+        process_group<D, CPL, G, VEC4, MASK, STRESS, ACC>(db, X, n, npad, r0, c0, g0 + G,
+                                                          nr, lane, xc, cacc, prow, fid);
+    }
+    if (ACC) {
+        float *pcol = Pm + (size_t)(g.ntc + I) * D * npad + c0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            if (VEC4) {
+#pragma unroll
+                for (int h = 0; h < CPL / 4; ++h)
+                    *reinterpret_cast<float4 *>(pcol + (size_t)k * npad + h * 256 + lane * 4) =
+                        make_float4(cacc[4 * h][k], cacc[4 * h + 1][k], cacc[4 * h + 2][k],
+                                    cacc[4 * h + 3][k]);
+            } else {
+#pragma unroll
+                for (int q = 0; q < CPL; ++q)
+                    pcol[(size_t)k * npad + lane_col<false>(lane, q)] = cacc[q][k];
+            }
+        }
+    }
+    if (STRESS) {
+        fid = wave_sum_d(fid);
+        if (lane == 0) F[(size_t)i * (g.nint + g.nbnd) + tile_off + tix] = fid;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Finalize: reduce the partial slots of row j, apply w_bb (B_b's entries are
+// -w_bb Delta/d), combine with W^-1 in FP64 (eq:update), store X_{t+1} and
+// accumulate its commensurability sum_{a<b} w_ab ||X^(a)_j - X^(b)_j||^2
+// from the stored FP32 values.
+// ---------------------------------------------------------------------------
+constexpr int FIN_BLOCK = 256;
+
+__device__ __forceinline__ double block_sum_d(double v, double *sh) {
+    v = wave_sum_d(v);
+    const int wv = threadIdx.x / WAVE;
+    if ((threadIdx.x & (WAVE - 1)) == 0) sh[wv] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int q = 0; q < (int)(blockDim.x / WAVE); ++q) s += sh[q];
+    return s;
+}
+
+template <int MM>
+__global__ __launch_bounds__(FIN_BLOCK) void finalize_kernel(
+    TriGeom g, int D, const float *__restrict__ P,
+    const double *__restrict__ Winv, const double *__restrict__ wmat,
+    float *__restrict__ Xout, double *__restrict__ comP,
+    const EmbedState *__restrict__ st, int want_com) {
+    __shared__ double sh[FIN_BLOCK / WAVE];
+    if (st->done) return;
+    const int m = g.m, npad = g.npad, ntc = g.ntc;
+    const int S = g.ntc + g.ntr;
+    const int j = blockIdx.x * FIN_BLOCK + threadIdx.x;
+    double com = 0.0;
+    if (j < g.n) {
+        // tiles holding row j as a row: (I, J) for J in [jlo, ntc);
+        // as a column: (I, Jc) for I in [0, ihi).
+        const int I = j / g.th, Jc = j / g.tw;
+        int jlo = (I * g.th) / g.tw;
+        while (jlo < ntc && !tile_exists(g, I, jlo)) ++jlo;
+        int ihi = 0;
+        while (ihi < g.ntr && tile_exists(g, ihi, Jc)) ++ihi;
+        const size_t slot = (size_t)D * npad;
+        for (int k = 0; k < D; ++k) {
+            double bx[MM];
+            for (int b = 0; b < m; ++b) {
+                const float *Pb = P + (size_t)b * S * slot + (size_t)k * npad + j;
+                double s = 0.0;
+                for (int q = 0; q < ihi; ++q) s += (double)Pb[(size_t)(ntc + q) * slot];
+                for (int q = jlo; q < ntc; ++q) s -= (double)Pb[(size_t)q * slot];
+                bx[b] = wmat[b * m + b] * s;
+            }
+            float xn[MM];
+            for (int a = 0; a < m; ++a) {
+                double v = 0.0;
+                for (int b = 0; b < m; ++b) v += Winv[a * m + b] * bx[b];
+                xn[a] = (float)v;
+                Xout[((size_t)a * D + k) * npad + j] = xn[a];
+            }
+            if (want_com)
+                for (int a = 0; a < m; ++a)
+                    for (int b = a + 1; b < m; ++b) {
+                        const double t = (double)xn[a] - (double)xn[b];
+                        com += wmat[a * m + b] * t * t;
+                    }
+        }
+    } else if (j < npad) {
+        for (int a = 0; a < m; ++a)
+            for (int k = 0; k < D; ++k) Xout[((size_t)a * D + k) * npad + j] = 0.f;
+    }
+    if (want_com) {
+        const double s = block_sum_d(com, sh);
+        if (threadIdx.x == 0) comP[blockIdx.x] = s;
+    }
+}
+
+__global__ __launch_bounds__(FIN_BLOCK) void com_kernel(
+    TriGeom g, int D, const float *__restrict__ Xs,
+    const double *__restrict__ wmat, double *__restrict__ comP) {
+    __shared__ double sh[FIN_BLOCK / WAVE];
+    const int m = g.m, npad = g.npad;
+    const int j = blockIdx.x * FIN_BLOCK + threadIdx.x;
+    double com = 0.0;
+    if (j < g.n)
+        for (int k = 0; k < D; ++k)
+            for (int a = 0; a < m; ++a)
+                for (int b = a + 1; b < m; ++b) {
+                    const double t = (double)Xs[((size_t)a * D + k) * npad + j] -
+                                     (double)Xs[((size_t)b * D + k) * npad + j];
+                    com += wmat[a * m + b] * t * t;
+                }
+    const double s = block_sum_d(com, sh);
+    if (threadIdx.x == 0) comP[blockIdx.x] = s;
+}
+
+// Deterministic FP64 reduction of the per-tile fidelity partials (weighted
+// by w_ii) and the commensurability partials, then Algorithm 2's stop test.
+constexpr int RED_BLOCK = 256;
+__global__ __launch_bounds__(RED_BLOCK) void reduce_kernel(
+    int m, int ntiles, const double *__restrict__ F,
+    const double *__restrict__ wmat, const double *__restrict__ comP,
+    int ncom, EmbedState *st, double *hist, int t, int check, int final_pass,
+    int iters, double tol, int tol_mode, double pairs) {
+    __shared__ double shf[RED_BLOCK], shc[RED_BLOCK];
+    if (st->done) return;
+    const int tid = threadIdx.x;
+    double f = 0.0, c = 0.0;
+    for (int i = 0; i < m; ++i) {
+        double fi = 0.0;
+        for (int q = tid; q < ntiles; q += RED_BLOCK) fi += F[(size_t)i * ntiles + q];
+        f += wmat[i * m + i] * fi;
+    }
+    for (int q = tid; q < ncom; q += RED_BLOCK) c += comP[q];
+    shf[tid] = f;
+    shc[tid] = c;
+    __syncthreads();
+    for (int s = RED_BLOCK / 2; s > 0; s >>= 1) {
+        if (tid < s) {
+            shf[tid] += shf[tid + s];
+            shc[tid] += shc[tid + s];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const double fid = shf[0], com = shc[0], sigma = fid + com;
+        hist[t] = sigma;
+        st->sigma = sigma;
+        st->fid = fid;
+        st->com = com;
+        if (check && tol > 0.0 && t > 0) {
+            const double thr = (tol_mode == 2) ? tol * pairs : tol * st->last;
+            if (st->last - sigma < thr) {
+                st->done = 1;
+                st->converged = 1;
+                st->iters_run = t;
+            }
+        }
+        if (check) st->last = sigma;
+        if (final_pass && !st->converged) st->iters_run = iters;
+    }
+}
+
+__global__ void init_state_kernel(EmbedState *st, double *hist, int nhist) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        st->done = 0;
+        st->iters_run = 0;
+        st->converged = 0;
+        st->pad = 0;
+        st->last = 0.0;
+        st->sigma = st->fid = st->com = 0.0;
+    }
+    if (i < nhist) hist[i] = __builtin_nan("");
+}
+
+__global__ void to_soa_kernel(TriGeom g, int D, const float *__restrict__ X,
+                              float *__restrict__ Xs) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int a = idx / g.npad, j = idx - a * g.npad;
+    if (a >= g.m) return;
+    for (int k = 0; k < D; ++k)
+        Xs[((size_t)a * D + k) * g.npad + j] =
+            (j < g.n) ? X[((size_t)a * g.n + j) * D + k] : 0.f;
+}
+
+__global__ void from_soa_kernel(TriGeom g, int D, const float *__restrict__ Xa,
+                                const float *__restrict__ Xb,
+                                const EmbedState *__restrict__ st,
+                                float *__restrict__ X) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int a = idx / g.n, j = idx - a * g.n;
+    if (a >= g.m) return;
+    const float *Xs = (st->iters_run & 1) ? Xb : Xa;
+    for (int k = 0; k < D; ++k)
+        X[((size_t)a * g.n + j) * D + k] = Xs[((size_t)a * D + k) * g.npad + j];
+}
+
+template <int D, int CPL, bool VEC4, bool MASK>
+void launch_bx_m(const TriGeom &g, const DeltaPtrs &dp, const float *Xs,
+                 const uint32_t *tiles, int off, int ntl, float *P, double *F,
+                 const EmbedState *st, bool stress, bool acc, hipStream_t s) {
+    if (ntl == 0) return;
+    const dim3 grid((unsigned)(g.m * ntl)), block(WAVE);
+    if (stress && acc)
+        bx_kernel<D, CPL, VEC4, MASK, true, true><<<grid, block, 0, s>>>(g, dp, Xs, tiles, off, ntl, P, F, st);
+    else if (acc)
+        bx_kernel<D, CPL, VEC4, MASK, false, true><<<grid, block, 0, s>>>(g, dp, Xs, tiles, off, ntl, P, F, st);
+    else
+        bx_kernel<D, CPL, VEC4, MASK, true, false><<<grid, block, 0, s>>>(g, dp, Xs, tiles, off, ntl, P, F, st);
+}
+
+template <int D, int CPL, bool VEC4>
+hipError_t launch_bx_t(const TriGeom &g, const DeltaPtrs &dp, const float *Xs,
+                       const uint32_t *tiles, float *P, double *F,
+                       const EmbedState *st, bool stress, bool acc, int part,
+                       hipStream_t s) {
+    if (part == 0)
+        launch_bx_m<D, CPL, VEC4, false>(g, dp, Xs, tiles, 0, g.nint, P, F, st, stress, acc, s);
+    else
+        launch_bx_m<D, CPL, VEC4, true>(g, dp, Xs, tiles, g.nint, g.nbnd, P, F, st, stress, acc, s);
+    return hipGetLastError();
+}
+
+template <int D>
+hipError_t launch_bx_d(const TriGeom &g, const DeltaPtrs &dp, const float *Xs,
+                       const uint32_t *tiles, float *P, double *F,
+                       const EmbedState *st, bool stress, bool acc, int part,
+                       hipStream_t s) {
+    if (g.cpl == 8)
+        return g.vec4 ? launch_bx_t<D, 8, true>(g, dp, Xs, tiles, P, F, st, stress, acc, part, s)
+                      : launch_bx_t<D, 8, false>(g, dp, Xs, tiles, P, F, st, stress, acc, part, s);
+    return g.vec4 ? launch_bx_t<D, 4, true>(g, dp, Xs, tiles, P, F, st, stress, acc, part, s)
+                  : launch_bx_t<D, 4, false>(g, dp, Xs, tiles, P, F, st, stress, acc, part, s);
+}
+
+}  // namespace
+
+hipError_t launch_bx(const TriGeom &g, int D, const DeltaPtrs &dp,
+                     const float *Xs, const uint32_t *tiles, float *P,
+                     double *F, const EmbedState *st, bool stress, bool acc,
+                     int part, hipStream_t s) {
+    switch (D) {
+    case 1: return launch_bx_d<1>(g, dp, Xs, tiles, P, F, st, stress, acc, part, s);
+    case 2: return launch_bx_d<2>(g, dp, Xs, tiles, P, F, st, stress, acc, part, s);
+    case 3: return launch_bx_d<3>(g, dp, Xs, tiles, P, F, st, stress, acc, part, s);
+    case 4: return launch_bx_d<4>(g, dp, Xs, tiles, P, F, st, stress, acc, part, s);
+    case 5: return launch_bx_d<5>(g, dp, Xs, tiles, P, F, st, stress, acc, part, s);
+    case 6: return launch_bx_d<6>(g, dp, Xs, tiles, P, F, st, stress, acc, part, s);
+    case 7: return launch_bx_d<7>(g, dp, Xs, tiles, P, F, st, stress, acc, part, s);
+    case 8: return launch_bx_d<8>(g, dp, Xs, tiles, P, F, st, stress, acc, part, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+int finalize_blocks(const TriGeom &g) { return (g.npad + FIN_BLOCK - 1) / FIN_BLOCK; }
+
+hipError_t launch_finalize(const TriGeom &g, int D, const float *P,
+                           const double *Winv, const double *wmat,
+                           float *Xout, double *comP, int ncomblk,
+                           const EmbedState *st, bool want_com,
+                           hipStream_t s) {
+    const dim3 grid((unsigned)ncomblk), block(FIN_BLOCK);
+    if (g.m <= 4)
+        finalize_kernel<4><<<grid, block, 0, s>>>(g, D, P, Winv, wmat, Xout, comP, st, want_com);
+    else if (g.m <= 8)
+        finalize_kernel<8><<<grid, block, 0, s>>>(g, D, P, Winv, wmat, Xout, comP, st, want_com);
+    else
+        finalize_kernel<MAXM><<<grid, block, 0, s>>>(g, D, P, Winv, wmat, Xout, comP, st, want_com);
+    return hipGetLastError();
+}
+
+hipError_t launch_com(const TriGeom &g, int D, const float *Xs,
+                      const double *wmat, double *comP, int ncomblk,
+                      hipStream_t s) {
+    com_kernel<<<dim3((unsigned)ncomblk), dim3(FIN_BLOCK), 0, s>>>(g, D, Xs, wmat, comP);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const TriGeom &g, const double *F,
+                         const double *wmat, const double *comP, int ncomblk,
+                         EmbedState *st, double *hist, int t, int check,
+                         int final_pass, int iters, double tol, int tol_mode,
+                         hipStream_t s) {
+    const double mn = (double)g.m * g.n;
+    reduce_kernel<<<1, RED_BLOCK, 0, s>>>(g.m, g.nint + g.nbnd, F, wmat, comP, ncomblk,
+                                          st, hist, t, check, final_pass, iters,
+                                          tol, tol_mode, 0.5 * mn * (mn - 1.0));
+    return hipGetLastError();
+}
+
+hipError_t launch_init_state(EmbedState *st, double *hist, int nhist,
+                             hipStream_t s) {
+    const int nb = (nhist + 255) / 256;
+    init_state_kernel<<<nb > 0 ? nb : 1, 256, 0, s>>>(st, hist, nhist);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_soa(const TriGeom &g, int D, const float *X, float *Xs,
+                         hipStream_t s) {
+    const size_t tot = (size_t)g.m * g.npad;
+    to_soa_kernel<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(g, D, X, Xs);
+    return hipGetLastError();
+}
+
+hipError_t launch_from_soa(const TriGeom &g, int D, const float *Xa,
+                           const float *Xb, const EmbedState *st, float *X,
+                           hipStream_t s) {
+    const size_t tot = (size_t)g.m * g.n;
+    from_soa_kernel<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(g, D, Xa, Xb, st, X);
+    return hipGetLastError();
+}
+
+}  // namespace fjofc

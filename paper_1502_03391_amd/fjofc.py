@@ -1,0 +1,204 @@
+"""Thin ctypes binding of libfjofc.so (include/fjofc.h).
+
+Argument marshalling only: every step of fast JOFC runs in the library's
+HIP kernels.  PyTorch provides device memory and the current stream.  The
+binding fails loudly when the library is missing; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfjofc.so")
+
+FJOFC_OK = 0
+FJOFC_TOL_NONE, FJOFC_TOL_REL, FJOFC_TOL_PAPER = 0, 1, 2
+FJOFC_MAX_M = 32
+FJOFC_MAX_D = 8
+
+# Every symbol include/fjofc.h declares.
+EXPORTS = ["fjofc_create", "fjofc_destroy", "fjofc_last_error", "fjofc_strerror",
+           "fjofc_embed", "fjofc_embed_w", "fjofc_stress", "fjofc_oos",
+           "fjofc_profile_enable", "fjofc_profile_read"]
+
+
+class FjofcResult(C.Structure):
+    _fields_ = [("iters_run", C.c_int), ("converged", C.c_int),
+                ("stress", C.c_double), ("stress_norm", C.c_double),
+                ("fidelity", C.c_double), ("commens", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class FjofcProfile(C.Structure):
+    _fields_ = [("stream_launches", C.c_int), ("stream_ms", C.c_double),
+                ("stream_bytes", C.c_double), ("edge_launches", C.c_int),
+                ("edge_ms", C.c_double), ("edge_bytes", C.c_double),
+                ("finalize_launches", C.c_int), ("finalize_ms", C.c_double),
+                ("reduce_launches", C.c_int), ("reduce_ms", C.c_double),
+                ("oos_launches", C.c_int), ("oos_ms", C.c_double),
+                ("oos_bytes", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class FjofcError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"fjofc error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libfjofc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python paper_1502_03391_amd/build.py`")
+        L = C.CDLL(LIB_PATH)
+        vp, ip, dp = C.c_void_p, C.c_int, C.c_double
+        L.fjofc_create.argtypes = [C.POINTER(vp), ip]
+        L.fjofc_destroy.argtypes = [vp]
+        L.fjofc_destroy.restype = None
+        L.fjofc_last_error.restype = C.c_char_p
+        L.fjofc_strerror.argtypes = [ip]
+        L.fjofc_strerror.restype = C.c_char_p
+        L.fjofc_embed.argtypes = [vp, C.POINTER(vp), ip, ip, C.POINTER(dp), ip, vp,
+                                  ip, dp, ip, ip, C.POINTER(dp),
+                                  C.POINTER(FjofcResult), vp]
+        L.fjofc_embed_w.argtypes = [vp, C.POINTER(vp), ip, ip, dp, ip, vp,
+                                    ip, dp, ip, ip, C.POINTER(dp),
+                                    C.POINTER(FjofcResult), vp]
+        L.fjofc_stress.argtypes = [vp, C.POINTER(vp), ip, ip, C.POINTER(dp), ip, vp,
+                                   C.POINTER(FjofcResult), vp]
+        L.fjofc_oos.argtypes = [vp, vp, ip, ip, ip, C.POINTER(dp), vp, ip, vp,
+                                ip, dp, vp, vp, vp, ip, vp]
+        L.fjofc_profile_enable.argtypes = [vp, ip]
+        L.fjofc_profile_read.argtypes = [vp, C.POINTER(FjofcProfile)]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != FJOFC_OK:
+        raise FjofcError(rc, lib().fjofc_last_error().decode())
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _wmat_arg(wmat, m):
+    w = np.ascontiguousarray(np.asarray(wmat, dtype=np.float64).reshape(m, m))
+    return w, w.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _dev_ptr(t, dtype, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor")
+    return t.data_ptr()
+
+
+class Context:
+    """Owns a fjofc_ctx (workspace, tile tables) on one device."""
+
+    def __init__(self, device: int = 0):
+        self._h = C.c_void_p()
+        _check(lib().fjofc_create(C.byref(self._h), int(device)))
+        self.device = device
+
+    def close(self):
+        if self._h:
+            lib().fjofc_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+
+def fjofc_embed(ctx: Context, delta: Sequence, wmat, X, iters: int,
+                tol: float = 0.0, tol_mode: int = FJOFC_TOL_REL,
+                stress_every: int = 1, want_hist: bool = False, stream=None):
+    """In-sample fJOFC.  delta: m CUDA float32 n x n tensors; X: CUDA
+    float32 (m n) x d tensor, X0 in, result out.  Returns (result dict,
+    stress history or None)."""
+    import torch
+    m = len(delta)
+    n = int(delta[0].shape[0])
+    ptrs = (C.c_void_p * m)(*[_dev_ptr(t, torch.float32, "delta") for t in delta])
+    _w, wp = _wmat_arg(wmat, m)
+    d = int(X.shape[1])
+    res = FjofcResult()
+    hist = np.empty(iters + 1) if want_hist else None
+    hp = hist.ctypes.data_as(C.POINTER(C.c_double)) if want_hist else None
+    _check(lib().fjofc_embed(ctx.handle, ptrs, m, n, wp, d,
+                             _dev_ptr(X, torch.float32, "X"), int(iters),
+                             float(tol), int(tol_mode), int(stress_every), hp,
+                             C.byref(res), _stream_ptr(stream)))
+    return res.as_dict(), hist
+
+
+def fjofc_stress(ctx: Context, delta: Sequence, wmat, X, stream=None):
+    """Raw stress of X (FP64 reduction on the GPU)."""
+    import torch
+    m = len(delta)
+    n = int(delta[0].shape[0])
+    ptrs = (C.c_void_p * m)(*[_dev_ptr(t, torch.float32, "delta") for t in delta])
+    _w, wp = _wmat_arg(wmat, m)
+    res = FjofcResult()
+    _check(lib().fjofc_stress(ctx.handle, ptrs, m, n, wp, int(X.shape[1]),
+                              _dev_ptr(X, torch.float32, "X"), C.byref(res),
+                              _stream_ptr(stream)))
+    return res.as_dict()
+
+
+def fjofc_oos(ctx: Context, X_in, wmat, delta_new, Y, iters: int,
+              tol: float = 0.0, target=None, stress_out=None, iters_out=None,
+              sync: bool = True, stream=None):
+    """Out-of-sample embedding.  X_in: (m n) x d; delta_new: k x m x n;
+    Y: k x m x d (starts in, results out); target / stress_out (float64, k)
+    and iters_out (int32, k) are optional CUDA tensors."""
+    import torch
+    k, m, n = (int(s) for s in delta_new.shape)
+    d = int(X_in.shape[1])
+    _w, wp = _wmat_arg(wmat, m)
+    tp = _dev_ptr(target, torch.float64, "target") if target is not None else None
+    sp = _dev_ptr(stress_out, torch.float64, "stress_out") if stress_out is not None else None
+    itp = _dev_ptr(iters_out, torch.int32, "iters_out") if iters_out is not None else None
+    _check(lib().fjofc_oos(ctx.handle, _dev_ptr(X_in, torch.float32, "X_in"), m, n, d,
+                           wp, _dev_ptr(delta_new, torch.float32, "delta_new"), k,
+                           _dev_ptr(Y, torch.float32, "Y"), int(iters), float(tol),
+                           tp, sp, itp, 1 if sync else 0, _stream_ptr(stream)))
+
+
+def fjofc_profile_enable(ctx: Context, on: bool = True):
+    """Start (and reset) or stop per-kernel event timing in the library."""
+    _check(lib().fjofc_profile_enable(ctx.handle, 1 if on else 0))
+
+
+def fjofc_profile_read(ctx: Context) -> dict:
+    """Summed kernel durations (ms) and algorithmic bytes since enabling."""
+    p = FjofcProfile()
+    _check(lib().fjofc_profile_read(ctx.handle, C.byref(p)))
+    return p.as_dict()

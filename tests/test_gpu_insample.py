@@ -1,0 +1,194 @@
+"""GPU parity of in-sample fJOFC (fjofc_embed / fjofc_stress) against the FP64
+CPU oracle, through the C ABI.
+
+Tolerances: the GPU computes distances, reciprocals and per-tile sums in
+FP32 and the combine, stress and stop rule in FP64.  After 200 transforms at
+the small in-sample workload the final stress must agree to 1e-5 relative
+and X to 1e-4 relative Frobenius.  Single transforms agree to ~1e-6
+relative per element (FP32 rounding of sums over n terms), checked at
+2e-5 of the largest entry.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from tests.conftest import gpu_available
+from workloads import generators as gen
+
+pytestmark = pytest.mark.gpu
+
+if gpu_available():
+    import torch
+    from paper_1502_03391_amd import fjofc
+    from oracle import structured as orc
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not gpu_available():
+        pytest.skip("no GPU")
+    c = fjofc.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _problem(seed, m, n, d, lat=3, sigma=0.2, w=0.5, wmat=None):
+    views, _, X0 = gen.latent_views(seed, n, m, lat, sigma, d)
+    delta = [gen.pairwise_dist_np(Y).astype(np.float32) for Y in views]
+    return delta, (wmat if wmat is not None else gen.uniform_wmat(m, w)), X0.astype(np.float32)
+
+
+def _general_wmat(m, seed=5):
+    rng = np.random.default_rng(seed)
+    W = rng.uniform(0.2, 2.0, size=(m, m))
+    W = 0.5 * (W + W.T)
+    np.fill_diagonal(W, rng.uniform(0.5, 2.0, size=m))
+    return W
+
+
+def _gpu_embed(ctx, delta, wmat, X0, iters, **kw):
+    dd = [_dev(x) for x in delta]
+    X = _dev(X0)
+    res, hist = fjofc.fjofc_embed(ctx, dd, wmat, X, iters, **kw)
+    torch.cuda.synchronize()
+    return X.cpu().numpy().astype(np.float64), res, hist
+
+
+def _rel_fro(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def test_config0_parity(ctx):
+    """m=2, n=200, d=2, 200 transforms, tol 1e-10 relative, stress every
+    transform: final stress to 1e-5 relative, X to 1e-4 relative Frobenius."""
+    P = gen.config0()
+    Xo, ro, ho = orc.embed(P.delta, P.wmat, P.X0, P.iters, tol=P.tol, tol_mode=1,
+                           stress_every=P.stress_every)
+    Xg, rg, hg = _gpu_embed(ctx, P.delta, P.wmat, P.X0, P.iters, tol=P.tol,
+                            tol_mode=1, stress_every=P.stress_every, want_hist=True)
+    assert rg["iters_run"] == ro["iters_run"]
+    assert rg["converged"] == ro["converged"]
+    assert abs(rg["stress"] - ro["stress"]) <= 1e-5 * ro["stress"]
+    assert _rel_fro(Xg, Xo) <= 1e-4
+    ok = ~np.isnan(ho)
+    assert np.array_equal(ok, ~np.isnan(hg))
+    np.testing.assert_allclose(hg[ok], ho[ok], rtol=1e-5)
+    # majorisation: non-increasing up to FP32 noise
+    assert np.all(np.diff(hg[ok]) <= 1e-6 * hg[ok][:-1])
+
+
+@pytest.mark.parametrize("tile", ["256:4", "128:8", "64:4", "512:8", "32:8"])
+@pytest.mark.parametrize("m,n,d", [(1, 2, 1), (2, 3, 2), (3, 7, 3), (2, 64, 5),
+                                   (2, 255, 2), (3, 256, 5), (2, 257, 3),
+                                   (4, 300, 8), (2, 513, 4), (3, 1000, 5),
+                                   (2, 1030, 6), (2, 777, 7)])
+def test_one_transform_parity(ctx, monkeypatch, tile, m, n, d):
+    """One Guttman transform and the stress of X0 and X1, across tile shapes,
+    ragged tails (n not a multiple of the tile or of 4) and all d."""
+    monkeypatch.setenv("FJOFC_TILE", tile)
+    wmat = _general_wmat(m, seed=n)
+    delta, _, X0 = _problem(100 + n + d, m, n, d, wmat=wmat)
+    X1o = orc.guttman(delta, wmat, X0)
+    Xg, rg, hg = _gpu_embed(ctx, delta, wmat, X0, 1, want_hist=True)
+    scale = np.abs(X1o).max()
+    np.testing.assert_allclose(Xg, X1o, rtol=0, atol=2e-5 * scale)
+    s0 = orc.stress(delta, wmat, X0)[0]
+    s1 = orc.stress(delta, wmat, X1o)[0]
+    assert hg[0] == pytest.approx(s0, rel=2e-6)
+    assert rg["stress"] == pytest.approx(s1, rel=2e-5)
+
+
+def test_stress_entry_point(ctx):
+    m, n, d = 3, 333, 4
+    wmat = _general_wmat(m)
+    delta, _, X0 = _problem(7, m, n, d, wmat=wmat)
+    r = fjofc.fjofc_stress(ctx, [_dev(x) for x in delta], wmat, _dev(X0))
+    s, fid, com = orc.stress(delta, wmat, X0)
+    assert r["stress"] == pytest.approx(s, rel=2e-6)
+    assert r["fidelity"] == pytest.approx(fid, rel=2e-6)
+    assert r["commens"] == pytest.approx(com, rel=2e-6)
+    assert r["iters_run"] == 0
+
+
+def test_many_iterations_parity_general_w(ctx):
+    m, n, d = 3, 600, 3
+    wmat = _general_wmat(m, seed=9)
+    delta, _, X0 = _problem(8, m, n, d, wmat=wmat)
+    Xo, ro, _ = orc.embed(delta, wmat, X0, 60, stress_every=7)
+    Xg, rg, _ = _gpu_embed(ctx, delta, wmat, X0, 60, stress_every=7)
+    assert rg["iters_run"] == 60
+    assert rg["stress"] == pytest.approx(ro["stress"], rel=1e-5)
+    assert _rel_fro(Xg, Xo) <= 1e-4
+
+
+def test_stop_rule_matches_oracle(ctx):
+    m, n, d = 2, 300, 2
+    delta, wmat, X0 = _problem(12, m, n, d)
+    for mode, tol, every in [(1, 1e-3, 1), (1, 2e-3, 5), (2, 1e-5, 1), (2, 3e-5, 2)]:
+        Xo, ro, ho = orc.embed(delta, wmat, X0, 500, tol=tol, tol_mode=mode, stress_every=every)
+        Xg, rg, hg = _gpu_embed(ctx, delta, wmat, X0, 500, tol=tol, tol_mode=mode,
+                                stress_every=every, want_hist=True)
+        t = ro["iters_run"]
+        assert ro["converged"] == 1 and 0 < t < 500
+        # the decision at the stop must not be within FP32 noise of the threshold
+        prev = ho[t - every]
+        thr = tol * prev if mode == 1 else tol * (m * n) * (m * n - 1) / 2
+        margin = abs((prev - ho[t]) - thr) / prev
+        if margin > 1e-5:
+            assert rg["iters_run"] == t and rg["converged"] == 1
+            assert _rel_fro(Xg, Xo) <= 1e-4
+
+
+def test_zero_iterations_and_coincident_points(ctx):
+    m, n, d = 2, 200, 3
+    delta, wmat, X0 = _problem(13, m, n, d)
+    X0[5] = X0[17]
+    X0[n + 3] = X0[n + 100]
+    Xg, rg, _ = _gpu_embed(ctx, delta, wmat, X0, 0)
+    np.testing.assert_array_equal(Xg, X0.astype(np.float64))
+    assert rg["stress"] == pytest.approx(orc.stress(delta, wmat, X0)[0], rel=2e-6)
+    X1o = orc.guttman(delta, wmat, X0)
+    Xg1, _, _ = _gpu_embed(ctx, delta, wmat, X0, 1)
+    assert np.all(np.isfinite(Xg1))
+    np.testing.assert_allclose(Xg1, X1o, rtol=0, atol=2e-5 * np.abs(X1o).max())
+
+
+def test_deterministic_and_resumable(ctx):
+    """Same inputs give bitwise-equal results; Algorithm 2's loop state is X
+    alone, so 10 + 10 transforms equal 20."""
+    m, n, d = 3, 700, 5
+    delta, wmat, X0 = _problem(14, m, n, d)
+    dd = [_dev(x) for x in delta]
+    Xa = _dev(X0)
+    fjofc.fjofc_embed(ctx, dd, wmat, Xa, 20)
+    Xb = _dev(X0)
+    fjofc.fjofc_embed(ctx, dd, wmat, Xb, 20)
+    Xc = _dev(X0)
+    fjofc.fjofc_embed(ctx, dd, wmat, Xc, 10)
+    fjofc.fjofc_embed(ctx, dd, wmat, Xc, 10)
+    torch.cuda.synchronize()
+    assert torch.equal(Xa, Xb)
+    assert torch.equal(Xa, Xc)
+
+
+def test_invalid_arguments_are_rejected(ctx):
+    delta, wmat, X0 = _problem(15, 2, 50, 2)
+    dd = [_dev(x) for x in delta]
+    bad = wmat.copy()
+    bad[0, 0] = 0.0
+    with pytest.raises(fjofc.FjofcError) as e:
+        fjofc.fjofc_embed(ctx, dd, bad, _dev(X0), 1)
+    assert e.value.code == 1
+    asym = wmat.copy()
+    asym[0, 1] = 0.7
+    with pytest.raises(fjofc.FjofcError):
+        fjofc.fjofc_embed(ctx, dd, asym, _dev(X0), 1)
+    with pytest.raises(fjofc.FjofcError):
+        fjofc.fjofc_embed(ctx, dd, wmat, _dev(np.zeros((100, 9))), 1)
+    with pytest.raises(fjofc.FjofcError):
+        fjofc.fjofc_embed(ctx, dd, wmat, _dev(X0), 1, stress_every=0)

@@ -1,0 +1,104 @@
+"""GPU parity of out-of-sample fJOFC (fjofc_oos) against the FP64 oracle.
+
+Per object the GPU sums n FP32 terms per modality; the update and the
+stress are FP64.  After `iters` transforms y agrees to 1e-4 relative of the
+configuration scale and the stress to 1e-5 relative; iteration counts of
+the stop rules agree except where the decision is within FP32 noise.
+"""
+import numpy as np
+import pytest
+
+from tests.conftest import gpu_available
+from workloads import generators as gen
+
+pytestmark = pytest.mark.gpu
+
+if gpu_available():
+    import torch
+    from paper_1502_03391_amd import fjofc
+    from oracle import structured as orc
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not gpu_available():
+        pytest.skip("no GPU")
+    c = fjofc.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(a, dt=np.float32):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).cuda()
+
+
+def _oos_problem(seed, m, n, d, k, lat=4, sigma=0.2, in_iters=30):
+    views, maps, X0 = gen.latent_views(seed, n, m, lat, sigma, d)
+    delta = [gen.pairwise_dist_np(Y).astype(np.float32) for Y in views]
+    wmat = gen.uniform_wmat(m, 0.5)
+    X, _, _ = orc.embed(delta, wmat, X0, in_iters)
+    X = X.astype(np.float32)
+    new = gen.oos_objects(seed + 1, k, maps, sigma)
+    dnew = np.stack([gen.cross_dist_np(new[i], views[i]) for i in range(m)], axis=1).astype(np.float32)
+    scale = np.sqrt((X.astype(np.float64) ** 2).mean())
+    Y0 = (gen.gaussian_start(seed + 2, (k, m, d)) * scale).astype(np.float32)
+    return X, wmat, dnew, Y0
+
+
+def _run(ctx, X, wmat, dnew, Y0, iters, **kw):
+    k = dnew.shape[0]
+    Y = _dev(Y0)
+    st = torch.empty(k, dtype=torch.float64, device="cuda")
+    it = torch.empty(k, dtype=torch.int32, device="cuda")
+    tg = kw.pop("target", None)
+    fjofc.fjofc_oos(ctx, _dev(X), wmat, _dev(dnew), Y, iters, stress_out=st, iters_out=it,
+                    target=_dev(tg, np.float64) if tg is not None else None, **kw)
+    torch.cuda.synchronize()
+    return Y.cpu().numpy().astype(np.float64), st.cpu().numpy(), it.cpu().numpy()
+
+
+@pytest.mark.parametrize("m,n,d,k", [(2, 200, 2, 9), (3, 257, 3, 17), (2, 1000, 5, 40),
+                                     (1, 100, 2, 8), (4, 64, 8, 5), (2, 3, 1, 3)])
+def test_oos_parity(ctx, m, n, d, k):
+    X, wmat, dnew, Y0 = _oos_problem(30 + n, m, n, d, k)
+    for iters in (0, 1, 25):
+        Yo, so, io = orc.oos(X, wmat, dnew, Y0, iters)
+        Yg, sg, ig = _run(ctx, X, wmat, dnew, Y0, iters)
+        assert np.array_equal(ig, io)
+        np.testing.assert_allclose(sg, so, rtol=1e-5)
+        scale = np.abs(X).max()
+        np.testing.assert_allclose(Yg, Yo, rtol=0, atol=1e-4 * scale)
+
+
+def test_oos_target_and_tol_stops(ctx):
+    m, n, d, k = 2, 500, 3, 24
+    X, wmat, dnew, Y0 = _oos_problem(77, m, n, d, k)
+    _, s50, _ = orc.oos(X, wmat, dnew, Y0, 50)
+    target = s50 * (1 + 1e-3)
+    Yo, so, io = orc.oos(X, wmat, dnew, Y0, 100, target=target)
+    Yg, sg, ig = _run(ctx, X, wmat, dnew, Y0, 100, target=target)
+    assert np.all(sg <= target)
+    # identical decisions except where the stress is within FP32 noise of target
+    agree = ig == io
+    assert agree.mean() >= 0.9
+    np.testing.assert_allclose(sg[agree], so[agree], rtol=1e-5)
+    Yo, so, io = orc.oos(X, wmat, dnew, Y0, 200, tol=1e-5)
+    Yg, sg, ig = _run(ctx, X, wmat, dnew, Y0, 200, tol=1e-5)
+    assert (ig == io).mean() >= 0.9
+
+
+def test_oos_leave_one_out_fixed_point(ctx):
+    """At a converged in-sample X*, object j embedded out of sample against
+    the other objects stays at X*_j (pin of the oracle, rerun on the GPU)."""
+    m, n, d = 2, 60, 2
+    views, _, X0 = gen.latent_views(91, n, m, 3, 0.1, d)
+    delta = [gen.pairwise_dist_np(Y).astype(np.float32) for Y in views]
+    wmat = gen.uniform_wmat(m, 0.5)
+    Xs, _, _ = orc.embed(delta, wmat, X0, 4000)
+    j = n - 1
+    keep = [i * n + r for i in range(m) for r in range(n) if r != j]
+    Xin = Xs[keep].astype(np.float32)
+    dnew = np.stack([delta[i][j, :j] for i in range(m)])[None].astype(np.float32)
+    y = np.stack([Xs[i * n + j] for i in range(m)])[None].astype(np.float32)
+    Yg, _, _ = _run(ctx, Xin, wmat, dnew, y, 20)
+    assert np.abs(Yg - y).max() < 1e-4 * np.abs(Xs).max()
