@@ -57,6 +57,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 2 GiB device copy (counter calibration)")
+    ap.add_argument("--iters", type=int, default=None,
+                    help="transforms per step (default: the workload's 300); "
+                         "for short profiled runs only")
     return ap.parse_args()
 
 
@@ -75,6 +78,8 @@ def main():
     torch.cuda.set_device(dev)
     spec = gen.config1_spec()
     m, n, d, iters, every = spec.m, spec.n, spec.d, spec.iters, spec.stress_every
+    if args.iters is not None:
+        iters = args.iters
     views, _, X0 = gen.config1_views(spec)
     delta = [gen.pairwise_dist_torch(Y, dev) for Y in views]
     wmat = gen.uniform_wmat(m, spec.w)

@@ -164,10 +164,10 @@ int fjofc_oos(fjofc_ctx *ctx, const float *X_in, int m, int n, int d,
  * counters.
  */
 typedef struct {
-    int stream_launches;     /* in-sample stream, interior tiles           */
+    int stream_launches;     /* in-sample stream forming B(X)X (every tile) */
     double stream_ms;
     double stream_bytes;
-    int edge_launches;       /* in-sample stream, diagonal / ragged tiles  */
+    int edge_launches;       /* in-sample stress-only stream (returned X)  */
     double edge_ms;
     double edge_bytes;
     int finalize_launches;   /* W^-1 combine and new X                     */

@@ -36,6 +36,7 @@ struct TriGeom {
     int npad;       // row pitch of SoA buffers (multiple of th and tw)
     int th, tw;     // tile height and width
     int cpl;        // columns per lane (4 or 8)
+    int variant;    // stream-kernel variant: (cpl, rows per group, buffering)
     int ntr, ntc;   // row / column blocks
     int nint;       // interior tiles per modality (no masking needed)
     int nbnd;       // boundary tiles per modality (diagonal or ragged)
@@ -57,18 +58,17 @@ inline size_t partial_floats(const TriGeom &g, int D) {
 
 // ---- launchers (insample.hip) ----------------------------------------
 // tiles: nint interior tiles then nbnd boundary tiles (I << 16 | J);
-// F: per-tile fidelity, [m][nint + nbnd].  part 0 launches the interior
-// tiles, part 1 the boundary tiles.
+// F: per-tile fidelity, [m][nint + nbnd].  One launch covers every tile.
 hipError_t launch_bx(const TriGeom &g, int D, const DeltaPtrs &dp,
                      const float *Xs, const uint32_t *tiles, float *P,
                      double *F, const EmbedState *st, bool stress, bool acc,
-                     int part, hipStream_t s);
+                     hipStream_t s);
 hipError_t launch_finalize(const TriGeom &g, int D, const float *P,
                            const double *Winv, const double *wmat,
                            float *Xout, double *comP, int ncomblk,
                            const EmbedState *st, bool want_com,
                            hipStream_t s);
-int finalize_blocks(const TriGeom &g);
+int finalize_blocks(const TriGeom &g, int D);
 hipError_t launch_com(const TriGeom &g, int D, const float *Xs,
                       const double *wmat, double *comP, int ncomblk,
                       hipStream_t s);

@@ -171,20 +171,28 @@ int get_tiles(fjofc_ctx *c, TriGeom &g, const uint32_t **out) {
     return FJOFC_OK;
 }
 
-// Tile shape of the in-sample stream: th rows x (64 cpl) columns.  The
-// FJOFC_TILE environment variable ("th:cpl", e.g. "256:4") overrides the
+// Stream-kernel variants: columns per lane, rows reduced per group, and
+// whether the row loads are double-buffered.
+struct Variant {
+    int cpl, g, dbuf;
+};
+constexpr Variant kVariants[] = {{4, 8, 1}, {4, 8, 0}, {4, 4, 1}, {8, 4, 1}, {8, 4, 0}, {8, 8, 0}};
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+// Tile shape of the in-sample stream: th rows x (64 cpl) columns, and the
+// kernel variant.  FJOFC_TILE ("th:variant", e.g. "256:0") overrides the
 // default.
-void choose_tiles(int n, int d, int &th, int &cpl) {
+void choose_tiles(int n, int d, int &th, int &variant) {
     (void)n;
     (void)d;
     th = 256;
-    cpl = 4;
+    variant = 5;  // 8 columns per lane, 8 rows per group, single-buffered
     if (const char *e = std::getenv("FJOFC_TILE")) {
         int a = 0, b = 0;
-        if (std::sscanf(e, "%d:%d", &a, &b) == 2 && (b == 4 || b == 8) && a >= 8 &&
+        if (std::sscanf(e, "%d:%d", &a, &b) == 2 && b >= 0 && b < kNumVariants && a >= 8 &&
             a <= 2048 && (a & (a - 1)) == 0) {
             th = a;
-            cpl = b;
+            variant = b;
         }
     }
 }
@@ -248,7 +256,8 @@ TriGeom make_geom(int m, int n, int d, const float *const *delta) {
     TriGeom g;
     g.n = n;
     g.m = m;
-    choose_tiles(n, d, g.th, g.cpl);
+    choose_tiles(n, d, g.th, g.variant);
+    g.cpl = kVariants[g.variant].cpl;
     g.tw = WAVE * g.cpl;
     const int unit = std::max(g.th, g.tw);
     g.npad = (n + unit - 1) / unit * unit;
@@ -273,7 +282,7 @@ struct InWork {
 int carve_insample(fjofc_ctx *c, const TriGeom &g, int D, int nhist, InWork &w) {
     Carve cv;
     const size_t xs = (size_t)g.m * D * g.npad;
-    const int ncom = finalize_blocks(g);
+    const int ncom = finalize_blocks(g, D);
     size_t oX0 = cv.take<float>(xs), oX1 = cv.take<float>(xs);
     size_t oP = cv.take<float>(partial_floats(g, D));
     size_t oF = cv.take<double>((size_t)g.m * (g.nint + g.nbnd));
@@ -349,19 +358,12 @@ int run_insample(fjofc_ctx *ctx, const float *const *delta, int m, int n,
     HIP_TRY(launch_to_soa(g, D, X, w.Xs[0], s));
     HIP_TRY(launch_com(g, D, w.Xs[0], w.wmat, w.comP, w.ncom, s));
 
-    // algorithmic bytes of the two stream launches: one FP32 read of every
+    // algorithmic bytes of a stream launch: one FP32 read of every
     // strict-upper-triangle entry of each block
-    const double pairs_int = (double)g.m * g.nint * g.th * g.tw;
     const double pairs_all = (double)g.m * 0.5 * n * (n - 1.0);
     auto stream_pass = [&](const float *Xcur, bool stress, bool acc) -> int {
-        {
-            Timed tm(ctx, K_STREAM, 4.0 * pairs_int, s);
-            HIP_TRY(launch_bx(g, D, dp, Xcur, tiles, w.P, w.F, w.st, stress, acc, 0, s));
-        }
-        {
-            Timed tm(ctx, K_EDGE, 4.0 * (pairs_all - pairs_int), s);
-            HIP_TRY(launch_bx(g, D, dp, Xcur, tiles, w.P, w.F, w.st, stress, acc, 1, s));
-        }
+        Timed tm(ctx, acc ? K_STREAM : K_EDGE, 4.0 * pairs_all, s);
+        HIP_TRY(launch_bx(g, D, dp, Xcur, tiles, w.P, w.F, w.st, stress, acc, s));
         return FJOFC_OK;
     };
     for (int p = 0; p < iters; ++p) {

@@ -259,20 +259,12 @@ __device__ __forceinline__ void process_group(
 // One wavefront streams one tile of the strict upper triangle.  MASK is set
 // for boundary tiles: those crossing the diagonal (only l > j counts) or
 // the ragged edge (rows or columns >= n).
-template <int D, int CPL, bool VEC4, bool MASK, bool STRESS, bool ACC>
-__global__ __launch_bounds__(WAVE) void bx_kernel(
-    TriGeom g, DeltaPtrs dp, const float *__restrict__ Xs,
-    const uint32_t *__restrict__ tiles, int tile_off, int ntl,
-    float *__restrict__ P, double *__restrict__ F,
-    const EmbedState *__restrict__ st) {
-    constexpr int G = (CPL == 4) ? 8 : 4;
-    if (st->done) return;
+template <int D, int CPL, int G, bool DBUF, bool VEC4, bool MASK, bool STRESS, bool ACC>
+__device__ __forceinline__ void stream_tile(
+    const TriGeom &g, const DeltaPtrs &dp, const float *__restrict__ Xs,
+    int i, int I, int J, int ftile, float *__restrict__ P,
+    double *__restrict__ F) {
     const int lane = threadIdx.x;
-    const int w = blockIdx.x;
-    const int i = w / ntl;
-    const int tix = w - i * ntl;
-    const uint32_t tt = tiles[tile_off + tix];
-    const int I = tt >> 16, J = tt & 0xffff;
     const int n = g.n, npad = g.npad;
     const int S = g.ntc + g.ntr;
     const float *__restrict__ dl = dp.p[i];
@@ -307,21 +299,32 @@ __global__ __launch_bounds__(WAVE) void bx_kernel(
     float *Pm = P + (size_t)i * S * D * npad;
     float *prow = Pm + (size_t)J * D * npad;
 
-    // Two row buffers used alternately (no register copies, so the loads of
-    // the next group stay in flight while the current group is computed).
-    float da[G][CPL], db[G][CPL];
-    load_rows<CPL, G, VEC4, MASK>(da, dl, n, r0, c0, lane, nr);
-    for (int g0 = 0; g0 < nr; g0 += 2 * G) {
-        if (g0 + G < nr)
-            load_rows<CPL, G, VEC4, MASK>(db, dl, n, r0 + g0 + G, c0, lane, nr - g0 - G);
-        process_group<D, CPL, G, VEC4, MASK, STRESS, ACC>(da, X, n, npad, r0, c0, g0, nr,
-                                                          lane, xc, cacc, prow, fid);
-        if (g0 + G >= nr) break;
-        if (g0 + 2 * G < nr)
-            load_rows<CPL, G, VEC4, MASK>(da, dl, n, r0 + g0 + 2 * G, c0, lane,
-                                          nr - g0 - 2 * G);
-        process_group<D, CPL, G, VEC4, MASK, STRESS, ACC>(db, X, n, npad, r0, c0, g0 + G,
-                                                          nr, lane, xc, cacc, prow, fid);
+    if (DBUF) {
+        // Two row buffers used alternately (no register copies, so the
+        // loads of the next group stay in flight while the current group
+        // is computed).
+        float da[G][CPL], db[G][CPL];
+        load_rows<CPL, G, VEC4, MASK>(da, dl, n, r0, c0, lane, nr);
+        for (int g0 = 0; g0 < nr; g0 += 2 * G) {
+            if (g0 + G < nr)
+                load_rows<CPL, G, VEC4, MASK>(db, dl, n, r0 + g0 + G, c0, lane, nr - g0 - G);
+            process_group<D, CPL, G, VEC4, MASK, STRESS, ACC>(da, X, n, npad, r0, c0, g0, nr,
+                                                              lane, xc, cacc, prow, fid);
+            if (g0 + G >= nr) break;
+            if (g0 + 2 * G < nr)
+                load_rows<CPL, G, VEC4, MASK>(da, dl, n, r0 + g0 + 2 * G, c0, lane,
+                                              nr - g0 - 2 * G);
+            process_group<D, CPL, G, VEC4, MASK, STRESS, ACC>(db, X, n, npad, r0, c0, g0 + G,
+                                                              nr, lane, xc, cacc, prow, fid);
+        }
+    } else {
+        // One row buffer: other wavefronts on the SIMD cover the load latency.
+        for (int g0 = 0; g0 < nr; g0 += G) {
+            float da[G][CPL];
+            load_rows<CPL, G, VEC4, MASK>(da, dl, n, r0 + g0, c0, lane, nr - g0);
+            process_group<D, CPL, G, VEC4, MASK, STRESS, ACC>(da, X, n, npad, r0, c0, g0, nr,
+                                                              lane, xc, cacc, prow, fid);
+        }
     }
     if (ACC) {
         float *pcol = Pm + (size_t)(g.ntc + I) * D * npad + c0;
@@ -342,7 +345,32 @@ __global__ __launch_bounds__(WAVE) void bx_kernel(
     }
     if (STRESS) {
         fid = wave_sum_d(fid);
-        if (lane == 0) F[(size_t)i * (g.nint + g.nbnd) + tile_off + tix] = fid;
+        if (lane == 0) F[(size_t)i * (g.nint + g.nbnd) + ftile] = fid;
+    }
+}
+
+// One launch streams every tile: blocks [0, m nint) take the interior
+// tiles of all modalities, the remaining m nbnd blocks the boundary tiles
+// (dispatched last: they are the cheap, half-empty ones).
+template <int D, int CPL, int G, bool DBUF, bool VEC4, bool STRESS, bool ACC>
+__global__ __launch_bounds__(WAVE) void bx_kernel(
+    TriGeom g, DeltaPtrs dp, const float *__restrict__ Xs,
+    const uint32_t *__restrict__ tiles, float *__restrict__ P,
+    double *__restrict__ F, const EmbedState *__restrict__ st) {
+    if (st->done) return;
+    const int w = blockIdx.x;
+    const int nin = g.m * g.nint;
+    if (w < nin) {
+        const int i = w / g.nint, t = w - i * g.nint;
+        const uint32_t tt = tiles[t];
+        stream_tile<D, CPL, G, DBUF, VEC4, false, STRESS, ACC>(g, dp, Xs, i, tt >> 16, tt & 0xffff,
+                                                      t, P, F);
+    } else {
+        const int wb = w - nin;
+        const int i = wb / g.nbnd, t = g.nint + (wb - i * g.nbnd);
+        const uint32_t tt = tiles[t];
+        stream_tile<D, CPL, G, DBUF, VEC4, true, STRESS, ACC>(g, dp, Xs, i, tt >> 16, tt & 0xffff,
+                                                     t, P, F);
     }
 }
 
@@ -365,6 +393,23 @@ __device__ __forceinline__ double block_sum_d(double v, double *sh) {
     return s;
 }
 
+// Sum of the slots [q0, q1) of one partial column (stride `slot` floats),
+// four independent FP64 accumulators so the loads overlap.
+__device__ __forceinline__ double slot_sum(const float *__restrict__ p, size_t slot,
+                                           int q0, int q1) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int q = q0;
+    for (; q + 4 <= q1; q += 4) {
+        a0 += (double)p[(size_t)q * slot];
+        a1 += (double)p[(size_t)(q + 1) * slot];
+        a2 += (double)p[(size_t)(q + 2) * slot];
+        a3 += (double)p[(size_t)(q + 3) * slot];
+    }
+    for (; q < q1; ++q) a0 += (double)p[(size_t)q * slot];
+    return (a0 + a1) + (a2 + a3);
+}
+
+// One thread per (row j, component k): blockIdx.y = k.
 template <int MM>
 __global__ __launch_bounds__(FIN_BLOCK) void finalize_kernel(
     TriGeom g, int D, const float *__restrict__ P,
@@ -375,10 +420,11 @@ __global__ __launch_bounds__(FIN_BLOCK) void finalize_kernel(
     if (st->done) return;
     const int m = g.m, npad = g.npad, ntc = g.ntc;
     const int S = g.ntc + g.ntr;
+    const int k = blockIdx.y;
     const int j = blockIdx.x * FIN_BLOCK + threadIdx.x;
     double com = 0.0;
     if (j < g.n) {
-        // tiles holding row j as a row: (I, J) for J in [jlo, ntc);
+        // tiles holding j as a row: (I, J) for J in [jlo, ntc);
         // as a column: (I, Jc) for I in [0, ihi).
         const int I = j / g.th, Jc = j / g.tw;
         int jlo = (I * g.th) / g.tw;
@@ -386,56 +432,52 @@ __global__ __launch_bounds__(FIN_BLOCK) void finalize_kernel(
         int ihi = 0;
         while (ihi < g.ntr && tile_exists(g, ihi, Jc)) ++ihi;
         const size_t slot = (size_t)D * npad;
-        for (int k = 0; k < D; ++k) {
-            double bx[MM];
-            for (int b = 0; b < m; ++b) {
-                const float *Pb = P + (size_t)b * S * slot + (size_t)k * npad + j;
-                double s = 0.0;
-                for (int q = 0; q < ihi; ++q) s += (double)Pb[(size_t)(ntc + q) * slot];
-                for (int q = jlo; q < ntc; ++q) s -= (double)Pb[(size_t)q * slot];
-                bx[b] = wmat[b * m + b] * s;
-            }
-            float xn[MM];
-            for (int a = 0; a < m; ++a) {
-                double v = 0.0;
-                for (int b = 0; b < m; ++b) v += Winv[a * m + b] * bx[b];
-                xn[a] = (float)v;
-                Xout[((size_t)a * D + k) * npad + j] = xn[a];
-            }
-            if (want_com)
-                for (int a = 0; a < m; ++a)
-                    for (int b = a + 1; b < m; ++b) {
-                        const double t = (double)xn[a] - (double)xn[b];
-                        com += wmat[a * m + b] * t * t;
-                    }
+        double bx[MM];
+        for (int b = 0; b < m; ++b) {
+            const float *Pb = P + (size_t)b * S * slot + (size_t)k * npad + j;
+            const double s = slot_sum(Pb, slot, ntc, ntc + ihi) - slot_sum(Pb, slot, jlo, ntc);
+            bx[b] = wmat[b * m + b] * s;
         }
+        float xn[MM];
+        for (int a = 0; a < m; ++a) {
+            double v = 0.0;
+            for (int b = 0; b < m; ++b) v += Winv[a * m + b] * bx[b];
+            xn[a] = (float)v;
+            Xout[((size_t)a * D + k) * npad + j] = xn[a];
+        }
+        if (want_com)
+            for (int a = 0; a < m; ++a)
+                for (int b = a + 1; b < m; ++b) {
+                    const double t = (double)xn[a] - (double)xn[b];
+                    com += wmat[a * m + b] * t * t;
+                }
     } else if (j < npad) {
-        for (int a = 0; a < m; ++a)
-            for (int k = 0; k < D; ++k) Xout[((size_t)a * D + k) * npad + j] = 0.f;
+        for (int a = 0; a < m; ++a) Xout[((size_t)a * D + k) * npad + j] = 0.f;
     }
     if (want_com) {
         const double s = block_sum_d(com, sh);
-        if (threadIdx.x == 0) comP[blockIdx.x] = s;
+        if (threadIdx.x == 0) comP[(size_t)k * gridDim.x + blockIdx.x] = s;
     }
 }
 
+// Commensurability of a configuration (same partial layout as finalize).
 __global__ __launch_bounds__(FIN_BLOCK) void com_kernel(
     TriGeom g, int D, const float *__restrict__ Xs,
     const double *__restrict__ wmat, double *__restrict__ comP) {
     __shared__ double sh[FIN_BLOCK / WAVE];
     const int m = g.m, npad = g.npad;
+    const int k = blockIdx.y;
     const int j = blockIdx.x * FIN_BLOCK + threadIdx.x;
     double com = 0.0;
     if (j < g.n)
-        for (int k = 0; k < D; ++k)
-            for (int a = 0; a < m; ++a)
-                for (int b = a + 1; b < m; ++b) {
-                    const double t = (double)Xs[((size_t)a * D + k) * npad + j] -
-                                     (double)Xs[((size_t)b * D + k) * npad + j];
-                    com += wmat[a * m + b] * t * t;
-                }
+        for (int a = 0; a < m; ++a)
+            for (int b = a + 1; b < m; ++b) {
+                const double t = (double)Xs[((size_t)a * D + k) * npad + j] -
+                                 (double)Xs[((size_t)b * D + k) * npad + j];
+                com += wmat[a * m + b] * t * t;
+            }
     const double s = block_sum_d(com, sh);
-    if (threadIdx.x == 0) comP[blockIdx.x] = s;
+    if (threadIdx.x == 0) comP[(size_t)k * gridDim.x + blockIdx.x] = s;
 }
 
 // Deterministic FP64 reduction of the per-tile fidelity partials (weighted
@@ -520,42 +562,46 @@ __global__ void from_soa_kernel(TriGeom g, int D, const float *__restrict__ Xa,
         X[((size_t)a * g.n + j) * D + k] = Xs[((size_t)a * D + k) * g.npad + j];
 }
 
-template <int D, int CPL, bool VEC4, bool MASK>
-void launch_bx_m(const TriGeom &g, const DeltaPtrs &dp, const float *Xs,
-                 const uint32_t *tiles, int off, int ntl, float *P, double *F,
-                 const EmbedState *st, bool stress, bool acc, hipStream_t s) {
-    if (ntl == 0) return;
-    const dim3 grid((unsigned)(g.m * ntl)), block(WAVE);
-    if (stress && acc)
-        bx_kernel<D, CPL, VEC4, MASK, true, true><<<grid, block, 0, s>>>(g, dp, Xs, tiles, off, ntl, P, F, st);
-    else if (acc)
-        bx_kernel<D, CPL, VEC4, MASK, false, true><<<grid, block, 0, s>>>(g, dp, Xs, tiles, off, ntl, P, F, st);
-    else
-        bx_kernel<D, CPL, VEC4, MASK, true, false><<<grid, block, 0, s>>>(g, dp, Xs, tiles, off, ntl, P, F, st);
-}
-
-template <int D, int CPL, bool VEC4>
+template <int D, int CPL, int G, bool DBUF, bool VEC4>
 hipError_t launch_bx_t(const TriGeom &g, const DeltaPtrs &dp, const float *Xs,
                        const uint32_t *tiles, float *P, double *F,
-                       const EmbedState *st, bool stress, bool acc, int part,
+                       const EmbedState *st, bool stress, bool acc,
                        hipStream_t s) {
-    if (part == 0)
-        launch_bx_m<D, CPL, VEC4, false>(g, dp, Xs, tiles, 0, g.nint, P, F, st, stress, acc, s);
+    const unsigned nb = (unsigned)(g.m * (g.nint + g.nbnd));
+    if (nb == 0) return hipSuccess;
+    const dim3 grid(nb), block(WAVE);
+    if (stress && acc)
+        bx_kernel<D, CPL, G, DBUF, VEC4, true, true><<<grid, block, 0, s>>>(g, dp, Xs, tiles, P, F, st);
+    else if (acc)
+        bx_kernel<D, CPL, G, DBUF, VEC4, false, true><<<grid, block, 0, s>>>(g, dp, Xs, tiles, P, F, st);
     else
-        launch_bx_m<D, CPL, VEC4, true>(g, dp, Xs, tiles, g.nint, g.nbnd, P, F, st, stress, acc, s);
+        bx_kernel<D, CPL, G, DBUF, VEC4, true, false><<<grid, block, 0, s>>>(g, dp, Xs, tiles, P, F, st);
     return hipGetLastError();
+}
+
+// Kernel variants: (columns per lane, rows per group, double-buffered rows).
+template <int D, int CPL, int G, bool DBUF>
+hipError_t launch_bx_v(const TriGeom &g, const DeltaPtrs &dp, const float *Xs,
+                       const uint32_t *tiles, float *P, double *F,
+                       const EmbedState *st, bool stress, bool acc,
+                       hipStream_t s) {
+    return g.vec4 ? launch_bx_t<D, CPL, G, DBUF, true>(g, dp, Xs, tiles, P, F, st, stress, acc, s)
+                  : launch_bx_t<D, CPL, G, DBUF, false>(g, dp, Xs, tiles, P, F, st, stress, acc, s);
 }
 
 template <int D>
 hipError_t launch_bx_d(const TriGeom &g, const DeltaPtrs &dp, const float *Xs,
                        const uint32_t *tiles, float *P, double *F,
-                       const EmbedState *st, bool stress, bool acc, int part,
+                       const EmbedState *st, bool stress, bool acc,
                        hipStream_t s) {
-    if (g.cpl == 8)
-        return g.vec4 ? launch_bx_t<D, 8, true>(g, dp, Xs, tiles, P, F, st, stress, acc, part, s)
-                      : launch_bx_t<D, 8, false>(g, dp, Xs, tiles, P, F, st, stress, acc, part, s);
-    return g.vec4 ? launch_bx_t<D, 4, true>(g, dp, Xs, tiles, P, F, st, stress, acc, part, s)
-                  : launch_bx_t<D, 4, false>(g, dp, Xs, tiles, P, F, st, stress, acc, part, s);
+    switch (g.variant) {
+    case 1: return launch_bx_v<D, 4, 8, false>(g, dp, Xs, tiles, P, F, st, stress, acc, s);
+    case 2: return launch_bx_v<D, 4, 4, true>(g, dp, Xs, tiles, P, F, st, stress, acc, s);
+    case 3: return launch_bx_v<D, 8, 4, true>(g, dp, Xs, tiles, P, F, st, stress, acc, s);
+    case 4: return launch_bx_v<D, 8, 4, false>(g, dp, Xs, tiles, P, F, st, stress, acc, s);
+    case 5: return launch_bx_v<D, 8, 8, false>(g, dp, Xs, tiles, P, F, st, stress, acc, s);
+    default: return launch_bx_v<D, 4, 8, true>(g, dp, Xs, tiles, P, F, st, stress, acc, s);
+    }
 }
 
 }  // namespace
@@ -563,28 +609,30 @@ hipError_t launch_bx_d(const TriGeom &g, const DeltaPtrs &dp, const float *Xs,
 hipError_t launch_bx(const TriGeom &g, int D, const DeltaPtrs &dp,
                      const float *Xs, const uint32_t *tiles, float *P,
                      double *F, const EmbedState *st, bool stress, bool acc,
-                     int part, hipStream_t s) {
+                     hipStream_t s) {
     switch (D) {
-    case 1: return launch_bx_d<1>(g, dp, Xs, tiles, P, F, st, stress, acc, part, s);
-    case 2: return launch_bx_d<2>(g, dp, Xs, tiles, P, F, st, stress, acc, part, s);
-    case 3: return launch_bx_d<3>(g, dp, Xs, tiles, P, F, st, stress, acc, part, s);
-    case 4: return launch_bx_d<4>(g, dp, Xs, tiles, P, F, st, stress, acc, part, s);
-    case 5: return launch_bx_d<5>(g, dp, Xs, tiles, P, F, st, stress, acc, part, s);
-    case 6: return launch_bx_d<6>(g, dp, Xs, tiles, P, F, st, stress, acc, part, s);
-    case 7: return launch_bx_d<7>(g, dp, Xs, tiles, P, F, st, stress, acc, part, s);
-    case 8: return launch_bx_d<8>(g, dp, Xs, tiles, P, F, st, stress, acc, part, s);
+    case 1: return launch_bx_d<1>(g, dp, Xs, tiles, P, F, st, stress, acc, s);
+    case 2: return launch_bx_d<2>(g, dp, Xs, tiles, P, F, st, stress, acc, s);
+    case 3: return launch_bx_d<3>(g, dp, Xs, tiles, P, F, st, stress, acc, s);
+    case 4: return launch_bx_d<4>(g, dp, Xs, tiles, P, F, st, stress, acc, s);
+    case 5: return launch_bx_d<5>(g, dp, Xs, tiles, P, F, st, stress, acc, s);
+    case 6: return launch_bx_d<6>(g, dp, Xs, tiles, P, F, st, stress, acc, s);
+    case 7: return launch_bx_d<7>(g, dp, Xs, tiles, P, F, st, stress, acc, s);
+    case 8: return launch_bx_d<8>(g, dp, Xs, tiles, P, F, st, stress, acc, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-int finalize_blocks(const TriGeom &g) { return (g.npad + FIN_BLOCK - 1) / FIN_BLOCK; }
+// Number of commensurability partials the finalize / com kernels write.
+int finalize_blocks(const TriGeom &g, int D) { return (g.npad + FIN_BLOCK - 1) / FIN_BLOCK * D; }
 
 hipError_t launch_finalize(const TriGeom &g, int D, const float *P,
                            const double *Winv, const double *wmat,
                            float *Xout, double *comP, int ncomblk,
                            const EmbedState *st, bool want_com,
                            hipStream_t s) {
-    const dim3 grid((unsigned)ncomblk), block(FIN_BLOCK);
+    const dim3 grid((unsigned)((g.npad + FIN_BLOCK - 1) / FIN_BLOCK), (unsigned)D), block(FIN_BLOCK);
+    (void)ncomblk;
     if (g.m <= 4)
         finalize_kernel<4><<<grid, block, 0, s>>>(g, D, P, Winv, wmat, Xout, comP, st, want_com);
     else if (g.m <= 8)
@@ -597,7 +645,9 @@ hipError_t launch_finalize(const TriGeom &g, int D, const float *P,
 hipError_t launch_com(const TriGeom &g, int D, const float *Xs,
                       const double *wmat, double *comP, int ncomblk,
                       hipStream_t s) {
-    com_kernel<<<dim3((unsigned)ncomblk), dim3(FIN_BLOCK), 0, s>>>(g, D, Xs, wmat, comP);
+    (void)ncomblk;
+    com_kernel<<<dim3((unsigned)((g.npad + FIN_BLOCK - 1) / FIN_BLOCK), (unsigned)D),
+                 dim3(FIN_BLOCK), 0, s>>>(g, D, Xs, wmat, comP);
     return hipGetLastError();
 }
 
