@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--iters", type=int, default=None,
                     help="transforms per step (default: the workload's 300); "
                          "for short profiled runs only")
+    ap.add_argument("--extras", default="oos,batched",
+                    help="comma list of extra workloads to measure after the main one "
+                         "(oos, batched, warmstart) or 'none'")
     return ap.parse_args()
 
 
@@ -155,8 +158,122 @@ def main():
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(delta, wmat, X0, m, n, every, args.cpu_seconds)
+    del delta, X, X0d
+    torch.cuda.empty_cache()
+    extras = [e for e in args.extras.split(",") if e and e != "none"]
+    out["extra"] = {}
+    if "oos" in extras:
+        out["extra"]["oos"] = bench_oos(ctx)
+    if "batched" in extras:
+        out["extra"]["batched"] = bench_batched(ctx)
     ctx.close()
     print(json.dumps(out), flush=True)
+
+
+def bench_oos(ctx):
+    """Out-of-sample workload: in-sample m=2, n=10000, d=5 (300 transforms),
+    then 50000 new objects from the same latent model, 100 transforms each,
+    4096 objects per launch."""
+    import numpy as np
+    import torch
+    from paper_1502_03391_amd import fjofc
+    from workloads import generators as gen
+    sp = gen.config2_spec()
+    dev = torch.device("cuda:0")
+    views, maps, X0 = gen.latent_views(sp.seed_in, sp.n, sp.m, sp.lat, sp.sigma, sp.d)
+    delta = [gen.pairwise_dist_torch(Y, dev) for Y in views]
+    wmat = gen.uniform_wmat(sp.m, sp.w)
+    Xin = torch.from_numpy(X0.astype(np.float32)).to(dev)
+    fjofc.fjofc_embed(ctx, delta, wmat, Xin, sp.in_iters, stress_every=sp.in_iters)
+    del delta
+    new = gen.oos_objects(sp.seed_new, sp.k, maps, sp.sigma)
+    dnew = torch.empty((sp.k, sp.m, sp.n), dtype=torch.float32, device=dev)
+    for i in range(sp.m):
+        dnew[:, i, :] = gen.cross_dist_torch(new[i], views[i], dev)
+    scale = float(torch.sqrt((Xin.double() ** 2).mean()))
+    Y0 = torch.from_numpy(gen.gaussian_start(sp.seed_start, (sp.k, sp.m, sp.d), scale)
+                          .astype(np.float32)).to(dev)
+    Y = torch.empty_like(Y0)
+    stress = torch.empty(sp.k, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    print(f"[bench] oos inputs ready: k={sp.k}", file=sys.stderr, flush=True)
+
+    def run():
+        Y.copy_(Y0)
+        for o0 in range(0, sp.k, sp.batch):
+            o1 = min(sp.k, o0 + sp.batch)
+            fjofc.fjofc_oos(ctx, Xin, wmat, dnew[o0:o1], Y[o0:o1], sp.iters,
+                            stress_out=stress[o0:o1], sync=False)
+        torch.cuda.synchronize()
+
+    run()
+    fjofc.fjofc_profile_enable(ctx, True)
+    t0 = time.perf_counter()
+    run()
+    t1 = time.perf_counter()
+    prof = fjofc.fjofc_profile_read(ctx)
+    fjofc.fjofc_profile_enable(ctx, False)
+    sec = t1 - t0
+    triples = sp.k * sp.m * sp.n * sp.iters
+    gbs = prof["oos_bytes"] / (prof["oos_ms"] * 1e-3) / 1e9
+    r = {"workload": sp.name, "objects": sp.k, "iters": sp.iters, "batch": sp.batch,
+         "seconds": sec, "triples_per_s": triples / sec, "objects_per_s": sp.k / sec,
+         "roofline": {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                      "frac": gbs / PEAK_HBM_GBS, "kernel": "oos_kernel",
+                      "launches": prof["oos_launches"],
+                      "avg_launch_ms": prof["oos_ms"] / max(1, prof["oos_launches"])},
+         "mean_stress": float(stress.mean())}
+    del dnew
+    torch.cuda.empty_cache()
+    return r
+
+
+def bench_batched(ctx, iters=150):
+    """512 independent problems, m ~ U{2,3,4}, n ~ U[64,2048], d ~ U{2,3,5},
+    150 transforms each, replayed from one captured HIP graph."""
+    import numpy as np
+    import torch
+    from paper_1502_03391_amd import fjofc
+    from workloads import generators as gen
+    dev = torch.device("cuda:0")
+    specs = gen.batched_specs(512)
+    probs, X0s = [], []
+    pairs = 0.0
+    for sp in specs:
+        views, _, X0 = gen.instance_views(sp)
+        dl = [gen.pairwise_dist_torch(Y, dev) for Y in views]
+        X0d = torch.from_numpy(X0.astype(np.float32)).to(dev)
+        probs.append((dl, gen.uniform_wmat(sp.m, 0.5), X0d.clone()))
+        X0s.append(X0d)
+        pairs += sp.m * sp.n * (sp.n - 1) / 2.0
+    torch.cuda.synchronize()
+    print(f"[bench] batched inputs ready: {len(specs)} problems", file=sys.stderr, flush=True)
+    b = fjofc.Batch(ctx, probs)
+
+    def reset():
+        for (_, _, X), X0 in zip(probs, X0s):
+            X.copy_(X0)
+        torch.cuda.synchronize()
+
+    reset()
+    b.run(iters, stress_every=iters, want_results=False)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(3):
+        reset()
+        t0 = time.perf_counter()
+        res = b.run(iters, stress_every=iters)
+        t1 = time.perf_counter()
+        times.append(t1 - t0)
+    sec = min(times)
+    b.close()
+    r = {"workload": "batched_512_uneven", "problems": len(specs), "iters": iters,
+         "pairs_per_sweep": pairs, "seconds": sec, "pairs_per_s": pairs * iters / sec,
+         "algorithmic_gbs": 4.0 * pairs * iters / sec / 1e9,
+         "mean_stress_norm": float(np.mean([x["stress_norm"] for x in res]))}
+    del probs
+    torch.cuda.empty_cache()
+    return r
 
 
 def cpu_baseline(delta, wmat, X0, m, n, every, target_s):

@@ -153,6 +153,42 @@ int fjofc_oos(fjofc_ctx *ctx, const float *X_in, int m, int n, int d,
               int *iters_out, int sync, void *stream);
 
 /*
+ * Batched in-sample fJOFC: many independent problems of different m, n, d
+ * advanced in lockstep (one stream launch per kernel variant and one
+ * combine launch per transform), the whole loop captured once into a HIP
+ * graph on a library-owned stream and replayed.  Each problem keeps its own
+ * stop rule (a stopped problem's tiles become no-ops).  Tile shapes come
+ * from the autotuned table, per (d, n).
+ */
+typedef struct {
+    int m, n, d;                /* as for fjofc_embed                        */
+    const float *const *delta;  /* host array of m device pointers           */
+    const double *wmat;         /* host m x m eq:W2 weights                  */
+    float *X;                   /* device (m*n) x d: X0 in, result out       */
+} fjofc_problem;
+
+typedef struct fjofc_batch fjofc_batch;
+
+/* Plan a batch: validate every problem, build tile lists and W^-1, allocate
+ * the batch workspace (device memory owned by the plan).  The pointers in
+ * probs must stay valid for the plan's lifetime; delta and wmat contents
+ * are read at each run, wmat at creation.                                  */
+int fjofc_batch_create(fjofc_ctx *ctx, const fjofc_problem *probs, int count,
+                       fjofc_batch **out);
+/* Run `iters` transforms of every problem (the first call with a given
+ * (iters, tol, tol_mode, stress_every) captures the graph; later calls
+ * replay it).  The run is ordered after prior work on `stream` and later
+ * work on `stream` waits for it.  res (host, count results) is optional;
+ * when given the call synchronises `stream`.                               */
+int fjofc_batch_run(fjofc_batch *b, int iters, double tol, int tol_mode,
+                    int stress_every, fjofc_result *res, void *stream);
+void fjofc_batch_destroy(fjofc_batch *b);
+/* create + run + destroy.                                                  */
+int fjofc_embed_batched(fjofc_ctx *ctx, const fjofc_problem *probs, int count,
+                        int iters, double tol, int tol_mode, int stress_every,
+                        fjofc_result *res, void *stream);
+
+/*
  * Per-kernel timing (tracing aid).  While enabled, every kernel launch of
  * fjofc_embed / fjofc_stress / fjofc_oos is bracketed by HIP events on the
  * caller's stream; fjofc_profile_read synchronises and returns the summed
@@ -177,6 +213,9 @@ typedef struct {
     int oos_launches;        /* out-of-sample kernel                       */
     double oos_ms;
     double oos_bytes;
+    int batch_launches;      /* whole batched graph replays                */
+    double batch_ms;
+    double batch_bytes;      /* 4 B per pair per transform, all problems   */
 } fjofc_profile;
 
 int fjofc_profile_enable(fjofc_ctx *ctx, int on);

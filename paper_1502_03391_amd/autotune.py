@@ -1,0 +1,105 @@
+"""Autotuner of the in-sample stream kernel's tile shape and variant.
+
+For each embedding dimension d and n-bucket it times every candidate
+(tile height, kernel variant) on the GPU through the public API (the
+library's per-launch HIP-event timing, with FJOFC_TILE forcing the
+candidate) and writes the fastest per bucket to ``tune_gfx950.txt`` next to
+libfjofc.so, which the library reads on first use (``FJOFC_TUNE_TABLE``
+overrides the path).  Cost per candidate = stream + finalize + reduce time
+per transform, averaged over a few transforms after a warm-up run.
+
+Run on the GPU:  python -m paper_1502_03391_amd.autotune [--dims 2,3,5]
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TABLE = os.path.join(HERE, "tune_gfx950.txt")
+
+# variant numbers as in the library: 0 = (4 cols/lane, 8-row groups,
+# double-buffered), 1 = (4, 8, single), 2 = (8, 4, single), 3 = (8, 8, single)
+CANDIDATES = [(64, 1), (128, 1), (256, 1), (128, 0), (256, 0),
+              (64, 2), (128, 2), (256, 2), (128, 3), (256, 3), (512, 3)]
+BUCKETS = [128, 256, 512, 1024, 2048, 4096, 8192, 16384, 1 << 30]
+
+
+def _rep_n(nmax: int) -> int:
+    return {1 << 30: 20000}.get(nmax, nmax - nmax // 8)
+
+
+def _time_candidate(ctx, fjofc, delta, wmat, X0, th, var, iters):
+    import torch
+    os.environ["FJOFC_TILE"] = f"{th}:{var}"
+    X = X0.clone()
+    fjofc.fjofc_embed(ctx, delta, wmat, X, 2, stress_every=iters)
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(2):
+        fjofc.fjofc_profile_enable(ctx, True)
+        X.copy_(X0)
+        fjofc.fjofc_embed(ctx, delta, wmat, X, iters, stress_every=iters)
+        p = fjofc.fjofc_profile_read(ctx)
+        fjofc.fjofc_profile_enable(ctx, False)
+        t = (p["stream_ms"] + p["finalize_ms"] + p["reduce_ms"]) / iters
+        best = t if best is None else min(best, t)
+    return best
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description="tune the in-sample stream kernel")
+    ap.add_argument("--dims", default="2,3,5")
+    ap.add_argument("--m", type=int, default=3)
+    ap.add_argument("--out", default=TABLE)
+    args = ap.parse_args(argv)
+    import numpy as np
+    import torch
+    from paper_1502_03391_amd import fjofc
+    sys.path.insert(0, os.path.dirname(HERE))
+    from workloads import generators as gen
+
+    dev = torch.device("cuda:0")
+    ctx = fjofc.Context(0)
+    rows = []
+    saved = os.environ.pop("FJOFC_TILE", None)
+    try:
+        for d in [int(x) for x in args.dims.split(",")]:
+            for nmax in BUCKETS:
+                n = _rep_n(nmax)
+                views, _, X0 = gen.latent_views(1000 + n + d, n, args.m, 8, 0.2, d)
+                delta = [gen.pairwise_dist_torch(Y, dev) for Y in views]
+                wmat = gen.uniform_wmat(args.m, 0.5)
+                X0d = torch.from_numpy(X0.astype(np.float32)).to(dev)
+                iters = max(10, min(60, int(2e10 / (args.m * n * n))))
+                best = None
+                for th, var in CANDIDATES:
+                    if th > max(n, 64):
+                        continue
+                    t = _time_candidate(ctx, fjofc, delta, wmat, X0d, th, var, iters)
+                    print(f"[tune] d={d} n={n} th={th} variant={var}: {t * 1e3:.1f} us/transform",
+                          flush=True)
+                    if best is None or t < best[0]:
+                        best = (t, th, var)
+                rows.append((d, nmax, best[1], best[2], best[0], n))
+                del delta
+                torch.cuda.empty_cache()
+    finally:
+        if saved is not None:
+            os.environ["FJOFC_TILE"] = saved
+        else:
+            os.environ.pop("FJOFC_TILE", None)
+        ctx.close()
+    with open(args.out, "w") as f:
+        f.write("# fJOFC stream-kernel tuning table for gfx950 (written by autotune.py)\n")
+        f.write(f"# {time.strftime('%Y-%m-%d')} {torch.cuda.get_device_name(0)}; m={args.m}\n")
+        f.write("# d n_max tile_height variant   (measured us/transform at n)\n")
+        for d, nmax, th, var, t, n in rows:
+            f.write(f"{d} {nmax} {th} {var}   # {t * 1e3:.1f} us at n={n}\n")
+    print(open(args.out).read(), flush=True)
+
+
+if __name__ == "__main__":
+    main()

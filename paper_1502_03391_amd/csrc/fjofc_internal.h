@@ -56,34 +56,61 @@ inline size_t partial_floats(const TriGeom &g, int D) {
     return (size_t)g.m * (g.ntc + g.ntr) * D * g.npad;
 }
 
+// One in-sample problem as the kernels see it (device-resident).
+struct InstDesc {
+    TriGeom g;
+    int D;
+    int ncom;           // commensurability partials (finalize blocks x D)
+    DeltaPtrs dp;
+    float *Xs[2];       // SoA [m][D][npad] configurations, double-buffered
+    float *P;           // partial sums
+    double *F;          // per-tile fidelity [m][nint + nbnd]
+    double *comP;       // commensurability partials
+    const double *Winv; // m x m
+    const double *wmat; // m x m
+    EmbedState *st;
+    double *hist;       // optional: stress history (iters + 1)
+    float *X;           // caller's (m n) x d configuration
+};
+
+// One wavefront's work: tile `tile` (I << 16 | J) of modality `mod` of
+// instance `inst`; ftile is its index in the instance's tile list.
+struct StreamItem {
+    int inst, mod;
+    uint32_t tile;
+    int ftile;
+};
+// One finalize / commensurability workgroup: rows [bx 256, bx 256 + 256)
+// and component k of instance `inst`.
+struct RowItem {
+    int inst, bx, k, pad;
+};
+
+constexpr int FIN_ROWS = 256;
+inline int commens_blocks(const TriGeom &g, int D) {
+    return (g.npad + FIN_ROWS - 1) / FIN_ROWS * D;
+}
+
 // ---- launchers (insample.hip) ----------------------------------------
-// tiles: nint interior tiles then nbnd boundary tiles (I << 16 | J);
-// F: per-tile fidelity, [m][nint + nbnd].  One launch covers every tile.
-hipError_t launch_bx(const TriGeom &g, int D, const DeltaPtrs &dp,
-                     const float *Xs, const uint32_t *tiles, float *P,
-                     double *F, const EmbedState *st, bool stress, bool acc,
-                     hipStream_t s);
-hipError_t launch_finalize(const TriGeom &g, int D, const float *P,
-                           const double *Winv, const double *wmat,
-                           float *Xout, double *comP, int ncomblk,
-                           const EmbedState *st, bool want_com,
-                           hipStream_t s);
-int finalize_blocks(const TriGeom &g, int D);
-hipError_t launch_com(const TriGeom &g, int D, const float *Xs,
-                      const double *wmat, double *comP, int ncomblk,
+// Stream kernels for one (D, variant, vec4) group of items; `cur` selects
+// the configuration buffer Xs[cur].
+hipError_t launch_stream(int D, int variant, int vec4, const InstDesc *insts,
+                         const StreamItem *items, int nitems, int cur,
+                         bool stress, bool acc, hipStream_t s);
+hipError_t launch_finalize(int maxm, const InstDesc *insts, const RowItem *rows,
+                           int nrows, int cur, bool want_com, hipStream_t s);
+hipError_t launch_com(const InstDesc *insts, const RowItem *rows, int nrows,
                       hipStream_t s);
-hipError_t launch_reduce(const TriGeom &g, const double *F,
-                         const double *wmat, const double *comP, int ncomblk,
-                         EmbedState *st, double *hist, int t, int check,
+// One workgroup per instance [0, count).
+hipError_t launch_reduce(const InstDesc *insts, int count, int t, int check,
                          int final_pass, int iters, double tol, int tol_mode,
                          hipStream_t s);
-hipError_t launch_init_state(EmbedState *st, double *hist, int nhist,
-                             hipStream_t s);
+hipError_t launch_init(const InstDesc *insts, int count, int nhist,
+                       hipStream_t s);
+hipError_t launch_copy_out(const InstDesc *insts, int count, hipStream_t s);
+// SoA conversion used by the out-of-sample path.
 hipError_t launch_to_soa(const TriGeom &g, int D, const float *X, float *Xs,
                          hipStream_t s);
-hipError_t launch_from_soa(const TriGeom &g, int D, const float *Xa,
-                           const float *Xb, const EmbedState *st, float *X,
-                           hipStream_t s);
 
 // ---- launchers (oos.hip) ---------------------------------------------
 struct OOSArgs {

@@ -8,7 +8,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <cstdlib>
+#include <dlfcn.h>
+#include <array>
 #include <map>
 #include <tuple>
 #include <string>
@@ -22,7 +25,6 @@ struct fjofc_ctx {
     size_t ws_bytes = 0;
     void *pinned = nullptr;      // small pinned host staging buffer
     size_t pinned_bytes = 0;
-    std::map<std::tuple<int, int, int>, uint32_t *> tiles;  // (n, th, tw) -> tile list
     // profiling: (kind, start, stop, bytes) per timed launch
     bool prof = false;
     struct Rec {
@@ -34,7 +36,7 @@ struct fjofc_ctx {
     std::vector<hipEvent_t> pool;
 };
 
-enum { K_STREAM = 0, K_EDGE, K_FIN, K_RED, K_OOS, K_KINDS };
+enum { K_STREAM = 0, K_EDGE, K_FIN, K_RED, K_OOS, K_BATCH, K_KINDS };
 
 namespace {
 
@@ -139,64 +141,6 @@ struct Timed {
     }
 };
 
-// Tile lists of the strict upper triangle: interior tiles (entirely above
-// the diagonal and inside n) first, then boundary tiles (crossing the
-// diagonal or the ragged edge), each in row-major order.
-bool tile_interior(const TriGeom &g, int I, int J) {
-    return (I + 1) * g.th <= g.n && (J + 1) * g.tw <= g.n && J * g.tw >= (I + 1) * g.th;
-}
-
-int get_tiles(fjofc_ctx *c, TriGeom &g, const uint32_t **out) {
-    std::vector<uint32_t> in, bd;
-    for (int I = 0; I < g.ntr; ++I)
-        for (int J = 0; J < g.ntc; ++J) {
-            if (!tile_exists(g, I, J)) continue;
-            (tile_interior(g, I, J) ? in : bd).push_back(((uint32_t)I << 16) | (uint32_t)J);
-        }
-    g.nint = (int)in.size();
-    g.nbnd = (int)bd.size();
-    const auto key = std::make_tuple(g.n, g.th, g.tw);
-    auto it = c->tiles.find(key);
-    if (it != c->tiles.end()) {
-        *out = it->second;
-        return FJOFC_OK;
-    }
-    in.insert(in.end(), bd.begin(), bd.end());
-    uint32_t *d = nullptr;
-    HIP_TRY(hipMalloc(&d, std::max<size_t>(1, in.size()) * sizeof(uint32_t)));
-    if (!in.empty())
-        HIP_TRY(hipMemcpy(d, in.data(), in.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
-    c->tiles[key] = d;
-    *out = d;
-    return FJOFC_OK;
-}
-
-// Stream-kernel variants: columns per lane, rows reduced per group, and
-// whether the row loads are double-buffered.
-struct Variant {
-    int cpl, g, dbuf;
-};
-constexpr Variant kVariants[] = {{4, 8, 1}, {4, 8, 0}, {4, 4, 1}, {8, 4, 1}, {8, 4, 0}, {8, 8, 0}};
-constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
-
-// Tile shape of the in-sample stream: th rows x (64 cpl) columns, and the
-// kernel variant.  FJOFC_TILE ("th:variant", e.g. "256:0") overrides the
-// default.
-void choose_tiles(int n, int d, int &th, int &variant) {
-    (void)n;
-    (void)d;
-    th = 256;
-    variant = 5;  // 8 columns per lane, 8 rows per group, single-buffered
-    if (const char *e = std::getenv("FJOFC_TILE")) {
-        int a = 0, b = 0;
-        if (std::sscanf(e, "%d:%d", &a, &b) == 2 && b >= 0 && b < kNumVariants && a >= 8 &&
-            a <= 2048 && (a & (a - 1)) == 0) {
-            th = a;
-            variant = b;
-        }
-    }
-}
-
 // eq:modW: diagonal n w_ii + sum_{j != i} w_ij, off-diagonal -w_ij.
 void wmod(int m, int n, const double *w, double *W) {
     for (int i = 0; i < m; ++i) {
@@ -252,8 +196,118 @@ int check_weights(int m, const double *wmat) {
     return FJOFC_OK;
 }
 
-TriGeom make_geom(int m, int n, int d, const float *const *delta) {
-    TriGeom g;
+// Tile lists of the strict upper triangle: interior tiles (entirely above
+// the diagonal and inside n) first, then boundary tiles (crossing the
+// diagonal or the ragged edge), each in row-major order.
+bool tile_interior(const TriGeom &g, int I, int J) {
+    return (I + 1) * g.th <= g.n && (J + 1) * g.tw <= g.n && J * g.tw >= (I + 1) * g.th;
+}
+
+// Stream-kernel variants: columns per lane, rows reduced per group, and
+// whether the row loads are double-buffered.  Numbering shared with the
+// kernels' dispatch.
+struct Variant {
+    int cpl, g, dbuf;
+};
+constexpr Variant kVariants[] = {{4, 8, 1}, {4, 8, 0}, {8, 4, 0}, {8, 8, 0}};
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+constexpr int kDefaultVariant = 3;
+
+// Tile shape of the in-sample stream: th rows x (64 cpl) columns and the
+// kernel variant.  Order of precedence: FJOFC_TILE ("th:variant"), the
+// autotuned table (FJOFC_TUNE_TABLE, else tune_gfx950.txt next to the
+// library), the built-in default.
+struct TuneRow {
+    int d, nmax, th, variant;
+};
+
+std::vector<TuneRow> &tune_table() {
+    static std::vector<TuneRow> rows;
+    static bool loaded = false;
+    if (loaded) return rows;
+    loaded = true;
+    std::string path;
+    if (const char *e = std::getenv("FJOFC_TUNE_TABLE")) {
+        path = e;
+    } else {
+        Dl_info info;
+        if (dladdr(reinterpret_cast<void *>(&tune_table), &info) && info.dli_fname) {
+            path = info.dli_fname;
+            const size_t sl = path.rfind('/');
+            path = (sl == std::string::npos ? std::string(".") : path.substr(0, sl)) +
+                   "/tune_gfx950.txt";
+        }
+    }
+    if (FILE *f = path.empty() ? nullptr : std::fopen(path.c_str(), "r")) {
+        char line[256];
+        while (std::fgets(line, sizeof line, f)) {
+            TuneRow r;
+            if (line[0] == '#') continue;
+            if (std::sscanf(line, "%d %d %d %d", &r.d, &r.nmax, &r.th, &r.variant) == 4 &&
+                r.variant >= 0 && r.variant < kNumVariants && r.th >= 8 && r.th <= 2048 &&
+                (r.th & (r.th - 1)) == 0)
+                rows.push_back(r);
+        }
+        std::fclose(f);
+    }
+    return rows;
+}
+
+void choose_tiles(int n, int d, int &th, int &variant) {
+    th = 256;
+    variant = kDefaultVariant;
+    int best = -1;
+    for (const TuneRow &r : tune_table())
+        if (r.d == d && n <= r.nmax && (best < 0 || r.nmax < best)) {
+            best = r.nmax;
+            th = r.th;
+            variant = r.variant;
+        }
+    if (const char *e = std::getenv("FJOFC_TILE")) {
+        int a = 0, b = 0;
+        if (std::sscanf(e, "%d:%d", &a, &b) == 2 && b >= 0 && b < kNumVariants && a >= 8 &&
+            a <= 2048 && (a & (a - 1)) == 0) {
+            th = a;
+            variant = b;
+        }
+    }
+}
+
+int check_problem(const float *const *delta, int m, int n, int d, const void *X) {
+    if (m < 1 || m > FJOFC_MAX_M) return fail(FJOFC_EINVAL, "m=%d outside [1,%d]", m, FJOFC_MAX_M);
+    if (n < 2 || n > 65535 * 64) return fail(FJOFC_EINVAL, "n=%d out of range", n);
+    if (d < 1 || d > FJOFC_MAX_D) return fail(FJOFC_EINVAL, "d=%d outside [1,%d]", d, FJOFC_MAX_D);
+    if (!delta) return fail(FJOFC_EINVAL, "delta is NULL");
+    for (int i = 0; i < m; ++i)
+        if (!delta[i]) return fail(FJOFC_EINVAL, "delta[%d] is NULL", i);
+    if (!X) return fail(FJOFC_EINVAL, "X is NULL");
+    return FJOFC_OK;
+}
+
+// Host-side plan of one in-sample problem: geometry, tile list, W^-1.
+struct HostInst {
+    TriGeom g{};
+    int D = 0;
+    DeltaPtrs dp{};
+    std::vector<uint32_t> tiles;  // interior then boundary
+    std::vector<double> Winv, wmat;
+    float *X = nullptr;
+    int nhist = 0;
+};
+
+int plan_instance(const float *const *delta, int m, int n, const double *wmat, int d,
+                  float *X, int nhist, HostInst &h) {
+    int rc = check_problem(delta, m, n, d, X);
+    if (rc) return rc;
+    rc = check_weights(m, wmat);
+    if (rc) return rc;
+    std::vector<double> W((size_t)m * m);
+    h.Winv.assign((size_t)m * m, 0.0);
+    h.wmat.assign(wmat, wmat + (size_t)m * m);
+    wmod(m, n, wmat, W.data());
+    if (!invert(m, W.data(), h.Winv.data()))
+        return fail(FJOFC_ESINGULAR, "eq:modW matrix is singular");
+    TriGeom &g = h.g;
     g.n = n;
     g.m = m;
     choose_tiles(n, d, g.th, g.variant);
@@ -263,144 +317,81 @@ TriGeom make_geom(int m, int n, int d, const float *const *delta) {
     g.npad = (n + unit - 1) / unit * unit;
     g.ntr = (n + g.th - 1) / g.th;
     g.ntc = (n + g.tw - 1) / g.tw;
-    g.nint = g.nbnd = 0;
     bool al = (n % 4) == 0;
     for (int i = 0; i < m; ++i)
         if ((reinterpret_cast<uintptr_t>(delta[i]) & 15) != 0) al = false;
     g.vec4 = al ? 1 : 0;
-    return g;
-}
-
-struct InWork {
-    float *Xs[2];
-    float *P;
-    double *F, *comP, *hist, *Winv, *wmat;
-    EmbedState *st;
-    int ncom;
-};
-
-int carve_insample(fjofc_ctx *c, const TriGeom &g, int D, int nhist, InWork &w) {
-    Carve cv;
-    const size_t xs = (size_t)g.m * D * g.npad;
-    const int ncom = finalize_blocks(g, D);
-    size_t oX0 = cv.take<float>(xs), oX1 = cv.take<float>(xs);
-    size_t oP = cv.take<float>(partial_floats(g, D));
-    size_t oF = cv.take<double>((size_t)g.m * (g.nint + g.nbnd));
-    size_t oC = cv.take<double>(ncom);
-    size_t oH = cv.take<double>(nhist);
-    size_t oW = cv.take<double>((size_t)g.m * g.m);
-    size_t oM = cv.take<double>((size_t)g.m * g.m);
-    size_t oS = cv.take<EmbedState>(1);
-    int rc = ensure_ws(c, cv.off);
-    if (rc) return rc;
-    char *b = static_cast<char *>(c->ws);
-    w.Xs[0] = reinterpret_cast<float *>(b + oX0);
-    w.Xs[1] = reinterpret_cast<float *>(b + oX1);
-    w.P = reinterpret_cast<float *>(b + oP);
-    w.F = reinterpret_cast<double *>(b + oF);
-    w.comP = reinterpret_cast<double *>(b + oC);
-    w.hist = reinterpret_cast<double *>(b + oH);
-    w.Winv = reinterpret_cast<double *>(b + oW);
-    w.wmat = reinterpret_cast<double *>(b + oM);
-    w.st = reinterpret_cast<EmbedState *>(b + oS);
-    w.ncom = ncom;
-    return FJOFC_OK;
-}
-
-int check_insample_args(const float *const *delta, int m, int n, int d,
-                        const void *X, fjofc_result *res) {
-    if (m < 1 || m > FJOFC_MAX_M) return fail(FJOFC_EINVAL, "m=%d outside [1,%d]", m, FJOFC_MAX_M);
-    if (n < 2 || n > (1 << 16) * 64) return fail(FJOFC_EINVAL, "n=%d out of range", n);
-    if (d < 1 || d > FJOFC_MAX_D) return fail(FJOFC_EINVAL, "d=%d outside [1,%d]", d, FJOFC_MAX_D);
-    if (!delta) return fail(FJOFC_EINVAL, "delta is NULL");
-    for (int i = 0; i < m; ++i)
-        if (!delta[i]) return fail(FJOFC_EINVAL, "delta[%d] is NULL", i);
-    if (!X) return fail(FJOFC_EINVAL, "X is NULL");
-    if (!res) return fail(FJOFC_EINVAL, "res is NULL");
-    return FJOFC_OK;
-}
-
-// Runs `iters` transforms (or only the stress of X when iters < 0).
-int run_insample(fjofc_ctx *ctx, const float *const *delta, int m, int n,
-                 const double *wmat, int d, float *X, int iters, double tol,
-                 int tol_mode, int stress_every, double *stress_hist,
-                 fjofc_result *res, hipStream_t s) {
-    const bool stress_only = iters < 0;
-    if (stress_only) iters = 0;
-    if (stress_every < 1) return fail(FJOFC_EINVAL, "stress_every must be >= 1");
-    if (tol_mode < FJOFC_TOL_NONE || tol_mode > FJOFC_TOL_PAPER)
-        return fail(FJOFC_EINVAL, "unknown tol_mode %d", tol_mode);
-    if (tol_mode == FJOFC_TOL_NONE) tol = 0.0;
-    int rc = check_weights(m, wmat);
-    if (rc) return rc;
-
-    std::vector<double> W((size_t)m * m), Wi((size_t)m * m);
-    wmod(m, n, wmat, W.data());
-    if (!invert(m, W.data(), Wi.data()))
-        return fail(FJOFC_ESINGULAR, "eq:modW matrix is singular");
-
-    TriGeom g = make_geom(m, n, d, delta);
-    const int D = d;
-    DeltaPtrs dp{};
-    for (int i = 0; i < m; ++i) dp.p[i] = delta[i];
-    const uint32_t *tiles = nullptr;
-    rc = get_tiles(ctx, g, &tiles);
-    if (rc) return rc;
-    InWork w;
-    rc = carve_insample(ctx, g, D, iters + 1, w);
-    if (rc) return rc;
-    rc = ensure_pinned(ctx, sizeof(EmbedState) + sizeof(double) * (size_t)(iters + 1) + 256);
-    if (rc) return rc;
-
-    HIP_TRY(hipMemcpyAsync(w.Winv, Wi.data(), sizeof(double) * m * m, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(w.wmat, wmat, sizeof(double) * m * m, hipMemcpyHostToDevice, s));
-    HIP_TRY(launch_init_state(w.st, w.hist, iters + 1, s));
-    HIP_TRY(launch_to_soa(g, D, X, w.Xs[0], s));
-    HIP_TRY(launch_com(g, D, w.Xs[0], w.wmat, w.comP, w.ncom, s));
-
-    // algorithmic bytes of a stream launch: one FP32 read of every
-    // strict-upper-triangle entry of each block
-    const double pairs_all = (double)g.m * 0.5 * n * (n - 1.0);
-    auto stream_pass = [&](const float *Xcur, bool stress, bool acc) -> int {
-        Timed tm(ctx, acc ? K_STREAM : K_EDGE, 4.0 * pairs_all, s);
-        HIP_TRY(launch_bx(g, D, dp, Xcur, tiles, w.P, w.F, w.st, stress, acc, s));
-        return FJOFC_OK;
-    };
-    for (int p = 0; p < iters; ++p) {
-        const bool due = (p % stress_every) == 0;
-        rc = stream_pass(w.Xs[p & 1], due, true);
-        if (rc) return rc;
-        if (due) {
-            Timed tm(ctx, K_RED, 0.0, s);
-            HIP_TRY(launch_reduce(g, w.F, w.wmat, w.comP, w.ncom, w.st, w.hist, p,
-                                  /*check=*/1, /*final=*/0, iters, tol, tol_mode, s));
+    std::vector<uint32_t> bd;
+    h.tiles.clear();
+    for (int I = 0; I < g.ntr; ++I)
+        for (int J = 0; J < g.ntc; ++J) {
+            if (!tile_exists(g, I, J)) continue;
+            (tile_interior(g, I, J) ? h.tiles : bd).push_back(((uint32_t)I << 16) | (uint32_t)J);
         }
-        const bool next_due = ((p + 1) % stress_every) == 0 || (p + 1) == iters;
-        Timed tm(ctx, K_FIN, 0.0, s);
-        HIP_TRY(launch_finalize(g, D, w.P, w.Winv, w.wmat, w.Xs[(p + 1) & 1], w.comP,
-                                w.ncom, w.st, next_due, s));
-    }
-    // stress of the returned configuration (and the checkpoint test at
-    // t = iters) unless the stop rule already fired.
-    rc = stream_pass(w.Xs[iters & 1], true, false);
-    if (rc) return rc;
-    {
-        Timed tm(ctx, K_RED, 0.0, s);
-        HIP_TRY(launch_reduce(g, w.F, w.wmat, w.comP, w.ncom, w.st, w.hist, iters,
-                              (iters % stress_every) == 0 ? 1 : 0, 1, iters, tol, tol_mode, s));
-    }
-    if (!stress_only)
-        HIP_TRY(launch_from_soa(g, D, w.Xs[0], w.Xs[1], w.st, X, s));
+    g.nint = (int)h.tiles.size();
+    g.nbnd = (int)bd.size();
+    h.tiles.insert(h.tiles.end(), bd.begin(), bd.end());
+    h.D = d;
+    for (int i = 0; i < m; ++i) h.dp.p[i] = delta[i];
+    h.X = X;
+    h.nhist = nhist;
+    return FJOFC_OK;
+}
 
-    char *pin = static_cast<char *>(ctx->pinned);
-    HIP_TRY(hipMemcpyAsync(pin, w.st, sizeof(EmbedState), hipMemcpyDeviceToHost, s));
-    if (stress_hist)
-        HIP_TRY(hipMemcpyAsync(pin + 256, w.hist, sizeof(double) * (iters + 1),
-                               hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    EmbedState st;
-    std::memcpy(&st, pin, sizeof st);
-    if (stress_hist) std::memcpy(stress_hist, pin + 256, sizeof(double) * (iters + 1));
+// Device buffers of one instance, carved from a workspace.
+void carve_instance(Carve &cv, const HostInst &h, size_t offs[9]) {
+    const TriGeom &g = h.g;
+    const size_t xs = (size_t)g.m * h.D * g.npad;
+    offs[0] = cv.take<float>(xs);
+    offs[1] = cv.take<float>(xs);
+    offs[2] = cv.take<float>(partial_floats(g, h.D));
+    offs[3] = cv.take<double>((size_t)g.m * (g.nint + g.nbnd));
+    offs[4] = cv.take<double>(commens_blocks(g, h.D));
+    offs[5] = cv.take<double>((size_t)g.m * g.m);
+    offs[6] = cv.take<double>((size_t)g.m * g.m);
+    offs[7] = 0;  // loop states are carved contiguously by the caller
+    offs[8] = cv.take<double>(std::max(1, h.nhist));
+}
+
+InstDesc make_desc(char *base, const HostInst &h, const size_t offs[9], EmbedState *st) {
+    InstDesc d{};
+    d.g = h.g;
+    d.D = h.D;
+    d.ncom = commens_blocks(h.g, h.D);
+    d.dp = h.dp;
+    d.Xs[0] = reinterpret_cast<float *>(base + offs[0]);
+    d.Xs[1] = reinterpret_cast<float *>(base + offs[1]);
+    d.P = reinterpret_cast<float *>(base + offs[2]);
+    d.F = reinterpret_cast<double *>(base + offs[3]);
+    d.comP = reinterpret_cast<double *>(base + offs[4]);
+    d.Winv = reinterpret_cast<const double *>(base + offs[5]);
+    d.wmat = reinterpret_cast<const double *>(base + offs[6]);
+    d.st = st;
+    d.hist = h.nhist > 0 ? reinterpret_cast<double *>(base + offs[8]) : nullptr;
+    d.X = h.X;
+    return d;
+}
+
+// Work items of one instance: interior tiles of every modality first, then
+// the boundary tiles (half-empty diagonal tiles dispatched last shorten the
+// tail of the launch).  `bnd` receives the boundary items when given, so a
+// batch can put all its boundary items after all interior ones.
+void append_items(int inst, const HostInst &h, std::vector<StreamItem> &items,
+                  std::vector<StreamItem> *bnd = nullptr) {
+    std::vector<StreamItem> &b = bnd ? *bnd : items;
+    for (int i = 0; i < h.g.m; ++i)
+        for (int t = 0; t < h.g.nint; ++t) items.push_back({inst, i, h.tiles[t], t});
+    for (int i = 0; i < h.g.m; ++i)
+        for (int t = h.g.nint; t < (int)h.tiles.size(); ++t) b.push_back({inst, i, h.tiles[t], t});
+}
+
+void append_rows(int inst, const HostInst &h, std::vector<RowItem> &rows) {
+    const int nbx = h.g.npad / FIN_ROWS;
+    for (int k = 0; k < h.D; ++k)
+        for (int bx = 0; bx < nbx; ++bx) rows.push_back({inst, bx, k, 0});
+}
+
+void fill_result(const EmbedState &st, int m, int n, fjofc_result *res) {
     const double mn = (double)m * n;
     res->iters_run = st.iters_run;
     res->converged = st.converged;
@@ -408,7 +399,166 @@ int run_insample(fjofc_ctx *ctx, const float *const *delta, int m, int n,
     res->stress_norm = st.sigma / (0.5 * mn * (mn - 1.0));
     res->fidelity = st.fid;
     res->commens = st.com;
+}
+
+int check_loop_args(int iters, double &tol, int tol_mode, int stress_every) {
+    if (iters < 0) return fail(FJOFC_EINVAL, "iters must be >= 0");
+    if (stress_every < 1) return fail(FJOFC_EINVAL, "stress_every must be >= 1");
+    if (tol_mode < FJOFC_TOL_NONE || tol_mode > FJOFC_TOL_PAPER)
+        return fail(FJOFC_EINVAL, "unknown tol_mode %d", tol_mode);
+    if (tol_mode == FJOFC_TOL_NONE) tol = 0.0;
     return FJOFC_OK;
+}
+
+// One stream launch of a transform: the items of one (D, variant, vec4)
+// kernel instance.
+struct StreamGroup {
+    int D, variant, vec4;
+    const StreamItem *items;
+    int nitems;
+    double bytes;  // algorithmic bytes of one launch
+};
+
+// Enqueue Algorithm 2's loop for instances advancing in lockstep.  Used
+// eagerly by fjofc_embed and under stream capture by the batched plan.
+int enqueue_loop(fjofc_ctx *ctx, const InstDesc *insts, int count, int maxm,
+                 const std::vector<StreamGroup> &groups, const RowItem *rows, int nrows,
+                 int iters, double tol, int tol_mode, int stress_every, int nhist,
+                 bool stress_only, hipStream_t s) {
+    HIP_TRY(launch_init(insts, count, nhist, s));
+    HIP_TRY(launch_com(insts, rows, nrows, s));
+    auto stream_pass = [&](int cur, bool stress, bool acc) -> int {
+        for (const StreamGroup &gr : groups) {
+            Timed tm(ctx, acc ? K_STREAM : K_EDGE, gr.bytes, s);
+            HIP_TRY(launch_stream(gr.D, gr.variant, gr.vec4, insts, gr.items, gr.nitems, cur,
+                                  stress, acc, s));
+        }
+        return FJOFC_OK;
+    };
+    for (int p = 0; p < iters; ++p) {
+        const bool due = (p % stress_every) == 0;
+        int rc = stream_pass(p & 1, due, true);
+        if (rc) return rc;
+        if (due) {
+            Timed tm(ctx, K_RED, 0.0, s);
+            HIP_TRY(launch_reduce(insts, count, p, 1, 0, iters, tol, tol_mode, s));
+        }
+        const bool next_due = ((p + 1) % stress_every) == 0 || (p + 1) == iters;
+        Timed tm(ctx, K_FIN, 0.0, s);
+        HIP_TRY(launch_finalize(maxm, insts, rows, nrows, p & 1, next_due, s));
+    }
+    // stress of the returned configuration (and the checkpoint test at
+    // t = iters) unless the stop rule already fired.
+    int rc = stream_pass(iters & 1, true, false);
+    if (rc) return rc;
+    {
+        Timed tm(ctx, K_RED, 0.0, s);
+        HIP_TRY(launch_reduce(insts, count, iters, (iters % stress_every) == 0 ? 1 : 0, 1, iters,
+                              tol, tol_mode, s));
+    }
+    if (!stress_only) HIP_TRY(launch_copy_out(insts, count, s));
+    return FJOFC_OK;
+}
+
+// Runs `iters` transforms of one problem (or only the stress of X when
+// iters < 0).
+int run_insample(fjofc_ctx *ctx, const float *const *delta, int m, int n,
+                 const double *wmat, int d, float *X, int iters, double tol,
+                 int tol_mode, int stress_every, double *stress_hist,
+                 fjofc_result *res, hipStream_t s) {
+    const bool stress_only = iters < 0;
+    if (stress_only) iters = 0;
+    int rc = check_loop_args(iters, tol, tol_mode, stress_every);
+    if (rc) return rc;
+    if (!res) return fail(FJOFC_EINVAL, "res is NULL");
+    HostInst h;
+    rc = plan_instance(delta, m, n, wmat, d, X, iters + 1, h);
+    if (rc) return rc;
+    std::vector<StreamItem> items;
+    std::vector<RowItem> rows;
+    append_items(0, h, items);
+    append_rows(0, h, rows);
+
+    Carve cv;
+    const size_t o_desc = cv.take<InstDesc>(1);
+    const size_t o_items = cv.take<StreamItem>(items.size());
+    const size_t o_rows = cv.take<RowItem>(rows.size());
+    const size_t o_st = cv.take<EmbedState>(1);
+    size_t offs[9];
+    carve_instance(cv, h, offs);
+    rc = ensure_ws(ctx, cv.off);
+    if (rc) return rc;
+    rc = ensure_pinned(ctx, sizeof(EmbedState) + sizeof(double) * (size_t)(iters + 1) + 256);
+    if (rc) return rc;
+    char *base = static_cast<char *>(ctx->ws);
+    const InstDesc desc = make_desc(base, h, offs, reinterpret_cast<EmbedState *>(base + o_st));
+    InstDesc *d_desc = reinterpret_cast<InstDesc *>(base + o_desc);
+    StreamItem *d_items = reinterpret_cast<StreamItem *>(base + o_items);
+    RowItem *d_rows = reinterpret_cast<RowItem *>(base + o_rows);
+    HIP_TRY(hipMemcpyAsync(d_desc, &desc, sizeof desc, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(StreamItem),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_rows, rows.data(), rows.size() * sizeof(RowItem),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(const_cast<double *>(desc.Winv), h.Winv.data(),
+                           sizeof(double) * m * m, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(const_cast<double *>(desc.wmat), wmat, sizeof(double) * m * m,
+                           hipMemcpyHostToDevice, s));
+    const double bytes = 4.0 * m * 0.5 * n * (n - 1.0);
+    std::vector<StreamGroup> groups{{d, h.g.variant, h.g.vec4, d_items, (int)items.size(), bytes}};
+    rc = enqueue_loop(ctx, d_desc, 1, m, groups, d_rows, (int)rows.size(), iters, tol, tol_mode,
+                      stress_every, iters + 1, stress_only, s);
+    if (rc) return rc;
+
+    char *pin = static_cast<char *>(ctx->pinned);
+    HIP_TRY(hipMemcpyAsync(pin, desc.st, sizeof(EmbedState), hipMemcpyDeviceToHost, s));
+    if (stress_hist)
+        HIP_TRY(hipMemcpyAsync(pin + 256, desc.hist, sizeof(double) * (iters + 1),
+                               hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    EmbedState st;
+    std::memcpy(&st, pin, sizeof st);
+    if (stress_hist) std::memcpy(stress_hist, pin + 256, sizeof(double) * (iters + 1));
+    fill_result(st, m, n, res);
+    return FJOFC_OK;
+}
+
+}  // namespace
+
+// A batch of independent in-sample problems advanced in lockstep; the whole
+// loop is captured once into a HIP graph on a library-owned stream and
+// replayed by every fjofc_batch_run with the same loop parameters.
+struct fjofc_batch {
+    fjofc_ctx *ctx = nullptr;
+    int count = 0, maxm = 0;
+    std::vector<HostInst> hi;
+    void *mem = nullptr;
+    size_t bytes = 0;
+    InstDesc *d_insts = nullptr;
+    std::vector<StreamGroup> groups;
+    RowItem *d_rows = nullptr;
+    int nrows = 0;
+    hipStream_t cs = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int key_iters = -1, key_every = -1, key_mode = -1;
+    double key_tol = -1.0;
+    EmbedState *pinned = nullptr;
+    EmbedState *d_st = nullptr;
+};
+
+namespace {
+
+void batch_free(fjofc_batch *b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+    if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    if (b->cs) (void)hipStreamDestroy(b->cs);
+    if (b->mem) (void)hipFree(b->mem);
+    if (b->pinned) (void)hipHostFree(b->pinned);
+    delete b;
 }
 
 }  // namespace
@@ -446,7 +596,6 @@ void fjofc_destroy(fjofc_ctx *c) {
     (void)hipDeviceSynchronize();
     if (c->ws) (void)hipFree(c->ws);
     if (c->pinned) (void)hipHostFree(c->pinned);
-    for (auto &kv : c->tiles) (void)hipFree(kv.second);
     for (auto &r : c->recs) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
@@ -460,8 +609,6 @@ int fjofc_embed(fjofc_ctx *ctx, const float *const *delta, int m, int n,
                 int tol_mode, int stress_every, double *stress_hist,
                 fjofc_result *res, void *stream) {
     if (!ctx) return fail(FJOFC_EINVAL, "ctx is NULL");
-    int rc = check_insample_args(delta, m, n, d, X, res);
-    if (rc) return rc;
     if (iters < 0) return fail(FJOFC_EINVAL, "iters must be >= 0");
     DeviceGuard dg(ctx->device);
     return run_insample(ctx, delta, m, n, wmat, d, X, iters, tol, tol_mode,
@@ -484,8 +631,6 @@ int fjofc_stress(fjofc_ctx *ctx, const float *const *delta, int m, int n,
                  const double *wmat, int d, const float *X,
                  fjofc_result *res, void *stream) {
     if (!ctx) return fail(FJOFC_EINVAL, "ctx is NULL");
-    int rc = check_insample_args(delta, m, n, d, X, res);
-    if (rc) return rc;
     DeviceGuard dg(ctx->device);
     return run_insample(ctx, delta, m, n, wmat, d, const_cast<float *>(X), -1, 0.0,
                         FJOFC_TOL_NONE, 1, nullptr, res,
@@ -595,7 +740,174 @@ int fjofc_profile_read(fjofc_ctx *ctx, fjofc_profile *out) {
     out->oos_launches = cnt[K_OOS];
     out->oos_ms = ms[K_OOS];
     out->oos_bytes = by[K_OOS];
+    out->batch_launches = cnt[K_BATCH];
+    out->batch_ms = ms[K_BATCH];
+    out->batch_bytes = by[K_BATCH];
     return FJOFC_OK;
+}
+
+
+int fjofc_batch_create(fjofc_ctx *ctx, const fjofc_problem *probs, int count,
+                       fjofc_batch **out) {
+    if (!ctx || !probs || !out) return fail(FJOFC_EINVAL, "NULL argument");
+    if (count < 1) return fail(FJOFC_EINVAL, "count must be >= 1");
+    DeviceGuard dg(ctx->device);
+    fjofc_batch *b = new fjofc_batch();
+    b->ctx = ctx;
+    b->count = count;
+    b->hi.resize(count);
+    for (int p = 0; p < count; ++p) {
+        const fjofc_problem &q = probs[p];
+        const int rc = plan_instance(q.delta, q.m, q.n, q.wmat, q.d, q.X, 0, b->hi[p]);
+        if (rc) {
+            batch_free(b);
+            return fail(rc, "problem %d: %s", p, g_err.c_str());
+        }
+        b->maxm = std::max(b->maxm, q.m);
+    }
+    std::map<std::tuple<int, int, int>, std::vector<StreamItem>> gitems, gbnd;
+    std::map<std::tuple<int, int, int>, double> gbytes;
+    std::vector<RowItem> rows;
+    // largest problems first within each group: long items start early
+    std::vector<int> order(count);
+    for (int p = 0; p < count; ++p) order[p] = p;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+        return (double)b->hi[a].g.m * b->hi[a].g.n * b->hi[a].g.n >
+               (double)b->hi[c].g.m * b->hi[c].g.n * b->hi[c].g.n;
+    });
+    for (int p : order) {
+        const HostInst &h = b->hi[p];
+        const auto key = std::make_tuple(h.D, h.g.variant, h.g.vec4);
+        append_items(p, h, gitems[key], &gbnd[key]);
+        gbytes[key] += 4.0 * h.g.m * 0.5 * h.g.n * (h.g.n - 1.0);
+    }
+    for (auto &kv : gitems) kv.second.insert(kv.second.end(), gbnd[kv.first].begin(), gbnd[kv.first].end());
+    for (int p = 0; p < count; ++p) append_rows(p, b->hi[p], rows);
+    Carve cv;
+    const size_t o_insts = cv.take<InstDesc>(count);
+    const size_t o_st = cv.take<EmbedState>(count);
+    std::vector<size_t> o_groups;
+    for (auto &kv : gitems) o_groups.push_back(cv.take<StreamItem>(kv.second.size()));
+    const size_t o_rows = cv.take<RowItem>(rows.size());
+    std::vector<std::array<size_t, 9>> offs(count);
+    for (int p = 0; p < count; ++p) carve_instance(cv, b->hi[p], offs[p].data());
+    if (hipMalloc(&b->mem, cv.off) != hipSuccess) {
+        b->mem = nullptr;
+        batch_free(b);
+        return fail(FJOFC_ENOMEM, "batch workspace of %zu bytes", cv.off);
+    }
+    b->bytes = cv.off;
+    char *base = static_cast<char *>(b->mem);
+    b->d_insts = reinterpret_cast<InstDesc *>(base + o_insts);
+    EmbedState *d_st = reinterpret_cast<EmbedState *>(base + o_st);
+    b->d_st = d_st;
+    std::vector<InstDesc> descs(count);
+    int rc = FJOFC_OK;
+    auto copy = [&](void *dst, const void *src, size_t nb) {
+        if (!rc && nb && hipMemcpy(dst, src, nb, hipMemcpyHostToDevice) != hipSuccess)
+            rc = fail(FJOFC_EHIP, "batch descriptor upload failed");
+    };
+    for (int p = 0; p < count; ++p) {
+        descs[p] = make_desc(base, b->hi[p], offs[p].data(), d_st + p);
+        copy(const_cast<double *>(descs[p].Winv), b->hi[p].Winv.data(),
+             sizeof(double) * b->hi[p].Winv.size());
+        copy(const_cast<double *>(descs[p].wmat), b->hi[p].wmat.data(),
+             sizeof(double) * b->hi[p].wmat.size());
+    }
+    copy(b->d_insts, descs.data(), sizeof(InstDesc) * count);
+    size_t gi = 0;
+    for (auto &kv : gitems) {
+        StreamItem *d = reinterpret_cast<StreamItem *>(base + o_groups[gi++]);
+        copy(d, kv.second.data(), kv.second.size() * sizeof(StreamItem));
+        b->groups.push_back({std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
+                             d, (int)kv.second.size(), gbytes[kv.first]});
+    }
+    b->d_rows = reinterpret_cast<RowItem *>(base + o_rows);
+    b->nrows = (int)rows.size();
+    copy(b->d_rows, rows.data(), rows.size() * sizeof(RowItem));
+    if (!rc && (hipStreamCreate(&b->cs) != hipSuccess ||
+                hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess))
+        rc = fail(FJOFC_EHIP, "batch stream/event creation failed");
+    if (!rc && hipHostMalloc(reinterpret_cast<void **>(&b->pinned), sizeof(EmbedState) * count,
+                             hipHostMallocDefault) != hipSuccess) {
+        b->pinned = nullptr;
+        rc = fail(FJOFC_ENOMEM, "pinned batch results");
+    }
+    if (rc) {
+        batch_free(b);
+        return rc;
+    }
+    *out = b;
+    return FJOFC_OK;
+}
+
+int fjofc_batch_run(fjofc_batch *b, int iters, double tol, int tol_mode, int stress_every,
+                    fjofc_result *res, void *stream) {
+    if (!b) return fail(FJOFC_EINVAL, "batch is NULL");
+    int rc = check_loop_args(iters, tol, tol_mode, stress_every);
+    if (rc) return rc;
+    fjofc_ctx *ctx = b->ctx;
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!b->exec || b->key_iters != iters || b->key_every != stress_every ||
+        b->key_mode != tol_mode || b->key_tol != tol) {
+        if (b->exec) (void)hipGraphExecDestroy(b->exec);
+        if (b->graph) (void)hipGraphDestroy(b->graph);
+        b->exec = nullptr;
+        b->graph = nullptr;
+        const bool prof = ctx->prof;
+        ctx->prof = false;  // no event records inside the captured graph
+        HIP_TRY(hipStreamBeginCapture(b->cs, hipStreamCaptureModeThreadLocal));
+        rc = enqueue_loop(ctx, b->d_insts, b->count, b->maxm, b->groups, b->d_rows, b->nrows,
+                          iters, tol, tol_mode, stress_every, 0, false, b->cs);
+        const hipError_t ec = hipStreamEndCapture(b->cs, &b->graph);
+        ctx->prof = prof;
+        if (rc) return rc;
+        if (ec != hipSuccess) return fail(FJOFC_EHIP, "graph capture failed: %s", hipGetErrorString(ec));
+        HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+        b->key_iters = iters;
+        b->key_every = stress_every;
+        b->key_mode = tol_mode;
+        b->key_tol = tol;
+    }
+    HIP_TRY(hipEventRecord(b->ev_in, s));
+    HIP_TRY(hipStreamWaitEvent(b->cs, b->ev_in, 0));
+    {
+        double bytes = 0.0;
+        for (const StreamGroup &gr : b->groups) bytes += gr.bytes;
+        Timed tm(ctx, K_BATCH, bytes * iters, b->cs);
+        HIP_TRY(hipGraphLaunch(b->exec, b->cs));
+    }
+    HIP_TRY(hipEventRecord(b->ev_out, b->cs));
+    HIP_TRY(hipStreamWaitEvent(s, b->ev_out, 0));
+    if (res) {
+        HIP_TRY(hipMemcpyAsync(b->pinned, b->d_st, sizeof(EmbedState) * b->count,
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (int p = 0; p < b->count; ++p)
+            fill_result(b->pinned[p], b->hi[p].g.m, b->hi[p].g.n, res + p);
+    }
+    return FJOFC_OK;
+}
+
+int fjofc_embed_batched(fjofc_ctx *ctx, const fjofc_problem *probs, int count, int iters,
+                        double tol, int tol_mode, int stress_every, fjofc_result *res,
+                        void *stream) {
+    fjofc_batch *b = nullptr;
+    int rc = fjofc_batch_create(ctx, probs, count, &b);
+    if (rc) return rc;
+    rc = fjofc_batch_run(b, iters, tol, tol_mode, stress_every, res, stream);
+    if (!res) (void)hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    fjofc_batch_destroy(b);
+    return rc;
+}
+
+void fjofc_batch_destroy(fjofc_batch *b) {
+    if (!b) return;
+    DeviceGuard dg(b->ctx->device);
+    (void)hipStreamSynchronize(b->cs);
+    batch_free(b);
 }
 
 }  // extern "C"

@@ -349,29 +349,23 @@ __device__ __forceinline__ void stream_tile(
     }
 }
 
-// One launch streams every tile: blocks [0, m nint) take the interior
-// tiles of all modalities, the remaining m nbnd blocks the boundary tiles
-// (dispatched last: they are the cheap, half-empty ones).
+// Stream kernel: one wavefront per work item.  Items of interior tiles run
+// the unmasked instance, boundary tiles (crossing the diagonal or the
+// ragged edge; listed after the interior ones) the masked instance.
 template <int D, int CPL, int G, bool DBUF, bool VEC4, bool STRESS, bool ACC>
 __global__ __launch_bounds__(WAVE) void bx_kernel(
-    TriGeom g, DeltaPtrs dp, const float *__restrict__ Xs,
-    const uint32_t *__restrict__ tiles, float *__restrict__ P,
-    double *__restrict__ F, const EmbedState *__restrict__ st) {
-    if (st->done) return;
-    const int w = blockIdx.x;
-    const int nin = g.m * g.nint;
-    if (w < nin) {
-        const int i = w / g.nint, t = w - i * g.nint;
-        const uint32_t tt = tiles[t];
-        stream_tile<D, CPL, G, DBUF, VEC4, false, STRESS, ACC>(g, dp, Xs, i, tt >> 16, tt & 0xffff,
-                                                      t, P, F);
-    } else {
-        const int wb = w - nin;
-        const int i = wb / g.nbnd, t = g.nint + (wb - i * g.nbnd);
-        const uint32_t tt = tiles[t];
-        stream_tile<D, CPL, G, DBUF, VEC4, true, STRESS, ACC>(g, dp, Xs, i, tt >> 16, tt & 0xffff,
-                                                     t, P, F);
-    }
+    const InstDesc *__restrict__ insts, const StreamItem *__restrict__ items, int cur) {
+    const StreamItem it = items[blockIdx.x];
+    const InstDesc &b = insts[it.inst];
+    if (b.st->done) return;
+    const float *Xs = b.Xs[cur];
+    const int I = it.tile >> 16, J = it.tile & 0xffff;
+    if (it.ftile < b.g.nint)
+        stream_tile<D, CPL, G, DBUF, VEC4, false, STRESS, ACC>(b.g, b.dp, Xs, it.mod, I, J,
+                                                               it.ftile, b.P, b.F);
+    else
+        stream_tile<D, CPL, G, DBUF, VEC4, true, STRESS, ACC>(b.g, b.dp, Xs, it.mod, I, J,
+                                                              it.ftile, b.P, b.F);
 }
 
 // ---------------------------------------------------------------------------
@@ -380,8 +374,6 @@ __global__ __launch_bounds__(WAVE) void bx_kernel(
 // accumulate its commensurability sum_{a<b} w_ab ||X^(a)_j - X^(b)_j||^2
 // from the stored FP32 values.
 // ---------------------------------------------------------------------------
-constexpr int FIN_BLOCK = 256;
-
 __device__ __forceinline__ double block_sum_d(double v, double *sh) {
     v = wave_sum_d(v);
     const int wv = threadIdx.x / WAVE;
@@ -409,19 +401,24 @@ __device__ __forceinline__ double slot_sum(const float *__restrict__ p, size_t s
     return (a0 + a1) + (a2 + a3);
 }
 
-// One thread per (row j, component k): blockIdx.y = k.
+// One thread per (row j, component k) of one instance.
 template <int MM>
-__global__ __launch_bounds__(FIN_BLOCK) void finalize_kernel(
-    TriGeom g, int D, const float *__restrict__ P,
-    const double *__restrict__ Winv, const double *__restrict__ wmat,
-    float *__restrict__ Xout, double *__restrict__ comP,
-    const EmbedState *__restrict__ st, int want_com) {
-    __shared__ double sh[FIN_BLOCK / WAVE];
-    if (st->done) return;
+__global__ __launch_bounds__(FIN_ROWS) void finalize_kernel(
+    const InstDesc *__restrict__ insts, const RowItem *__restrict__ rows, int cur,
+    int want_com) {
+    __shared__ double sh[FIN_ROWS / WAVE];
+    const RowItem ri = rows[blockIdx.x];
+    const InstDesc &b = insts[ri.inst];
+    if (b.st->done) return;
+    const TriGeom &g = b.g;
+    const int D = b.D, k = ri.k;
     const int m = g.m, npad = g.npad, ntc = g.ntc;
     const int S = g.ntc + g.ntr;
-    const int k = blockIdx.y;
-    const int j = blockIdx.x * FIN_BLOCK + threadIdx.x;
+    const float *__restrict__ P = b.P;
+    const double *__restrict__ Winv = b.Winv;
+    const double *__restrict__ wmat = b.wmat;
+    float *__restrict__ Xout = b.Xs[cur ^ 1];
+    const int j = ri.bx * FIN_ROWS + threadIdx.x;
     double com = 0.0;
     if (j < g.n) {
         // tiles holding j as a row: (I, J) for J in [jlo, ntc);
@@ -433,71 +430,75 @@ __global__ __launch_bounds__(FIN_BLOCK) void finalize_kernel(
         while (ihi < g.ntr && tile_exists(g, ihi, Jc)) ++ihi;
         const size_t slot = (size_t)D * npad;
         double bx[MM];
-        for (int b = 0; b < m; ++b) {
-            const float *Pb = P + (size_t)b * S * slot + (size_t)k * npad + j;
+        for (int q = 0; q < m; ++q) {
+            const float *Pb = P + (size_t)q * S * slot + (size_t)k * npad + j;
             const double s = slot_sum(Pb, slot, ntc, ntc + ihi) - slot_sum(Pb, slot, jlo, ntc);
-            bx[b] = wmat[b * m + b] * s;
+            bx[q] = wmat[q * m + q] * s;
         }
         float xn[MM];
         for (int a = 0; a < m; ++a) {
             double v = 0.0;
-            for (int b = 0; b < m; ++b) v += Winv[a * m + b] * bx[b];
+            for (int q = 0; q < m; ++q) v += Winv[a * m + q] * bx[q];
             xn[a] = (float)v;
             Xout[((size_t)a * D + k) * npad + j] = xn[a];
         }
         if (want_com)
             for (int a = 0; a < m; ++a)
-                for (int b = a + 1; b < m; ++b) {
-                    const double t = (double)xn[a] - (double)xn[b];
-                    com += wmat[a * m + b] * t * t;
+                for (int q = a + 1; q < m; ++q) {
+                    const double t = (double)xn[a] - (double)xn[q];
+                    com += wmat[a * m + q] * t * t;
                 }
     } else if (j < npad) {
         for (int a = 0; a < m; ++a) Xout[((size_t)a * D + k) * npad + j] = 0.f;
     }
     if (want_com) {
         const double s = block_sum_d(com, sh);
-        if (threadIdx.x == 0) comP[(size_t)k * gridDim.x + blockIdx.x] = s;
+        if (threadIdx.x == 0) b.comP[(size_t)k * (npad / FIN_ROWS) + ri.bx] = s;
     }
 }
 
-// Commensurability of a configuration (same partial layout as finalize).
-__global__ __launch_bounds__(FIN_BLOCK) void com_kernel(
-    TriGeom g, int D, const float *__restrict__ Xs,
-    const double *__restrict__ wmat, double *__restrict__ comP) {
-    __shared__ double sh[FIN_BLOCK / WAVE];
-    const int m = g.m, npad = g.npad;
-    const int k = blockIdx.y;
-    const int j = blockIdx.x * FIN_BLOCK + threadIdx.x;
+// Commensurability of X_0 (same partial layout as the finalize).
+__global__ __launch_bounds__(FIN_ROWS) void com_kernel(
+    const InstDesc *__restrict__ insts, const RowItem *__restrict__ rows) {
+    __shared__ double sh[FIN_ROWS / WAVE];
+    const RowItem ri = rows[blockIdx.x];
+    const InstDesc &b = insts[ri.inst];
+    const TriGeom &g = b.g;
+    const int D = b.D, k = ri.k, m = g.m, npad = g.npad;
+    const float *__restrict__ Xs = b.Xs[0];
+    const int j = ri.bx * FIN_ROWS + threadIdx.x;
     double com = 0.0;
     if (j < g.n)
         for (int a = 0; a < m; ++a)
-            for (int b = a + 1; b < m; ++b) {
+            for (int q = a + 1; q < m; ++q) {
                 const double t = (double)Xs[((size_t)a * D + k) * npad + j] -
-                                 (double)Xs[((size_t)b * D + k) * npad + j];
-                com += wmat[a * m + b] * t * t;
+                                 (double)Xs[((size_t)q * D + k) * npad + j];
+                com += b.wmat[a * m + q] * t * t;
             }
     const double s = block_sum_d(com, sh);
-    if (threadIdx.x == 0) comP[(size_t)k * gridDim.x + blockIdx.x] = s;
+    if (threadIdx.x == 0) b.comP[(size_t)k * (npad / FIN_ROWS) + ri.bx] = s;
 }
 
 // Deterministic FP64 reduction of the per-tile fidelity partials (weighted
 // by w_ii) and the commensurability partials, then Algorithm 2's stop test.
+// One workgroup per instance.
 constexpr int RED_BLOCK = 256;
 __global__ __launch_bounds__(RED_BLOCK) void reduce_kernel(
-    int m, int ntiles, const double *__restrict__ F,
-    const double *__restrict__ wmat, const double *__restrict__ comP,
-    int ncom, EmbedState *st, double *hist, int t, int check, int final_pass,
-    int iters, double tol, int tol_mode, double pairs) {
+    const InstDesc *__restrict__ insts, int t, int check, int final_pass, int iters,
+    double tol, int tol_mode) {
     __shared__ double shf[RED_BLOCK], shc[RED_BLOCK];
+    const InstDesc &b = insts[blockIdx.x];
+    EmbedState *st = b.st;
     if (st->done) return;
     const int tid = threadIdx.x;
+    const int m = b.g.m, ntiles = b.g.nint + b.g.nbnd;
     double f = 0.0, c = 0.0;
     for (int i = 0; i < m; ++i) {
         double fi = 0.0;
-        for (int q = tid; q < ntiles; q += RED_BLOCK) fi += F[(size_t)i * ntiles + q];
-        f += wmat[i * m + i] * fi;
+        for (int q = tid; q < ntiles; q += RED_BLOCK) fi += b.F[(size_t)i * ntiles + q];
+        f += b.wmat[i * m + i] * fi;
     }
-    for (int q = tid; q < ncom; q += RED_BLOCK) c += comP[q];
+    for (int q = tid; q < b.ncom; q += RED_BLOCK) c += b.comP[q];
     shf[tid] = f;
     shc[tid] = c;
     __syncthreads();
@@ -510,12 +511,13 @@ __global__ __launch_bounds__(RED_BLOCK) void reduce_kernel(
     }
     if (tid == 0) {
         const double fid = shf[0], com = shc[0], sigma = fid + com;
-        hist[t] = sigma;
+        const double mn = (double)m * b.g.n;
+        if (b.hist) b.hist[t] = sigma;
         st->sigma = sigma;
         st->fid = fid;
         st->com = com;
         if (check && tol > 0.0 && t > 0) {
-            const double thr = (tol_mode == 2) ? tol * pairs : tol * st->last;
+            const double thr = (tol_mode == 2) ? tol * 0.5 * mn * (mn - 1.0) : tol * st->last;
             if (st->last - sigma < thr) {
                 st->done = 1;
                 st->converged = 1;
@@ -527,9 +529,14 @@ __global__ __launch_bounds__(RED_BLOCK) void reduce_kernel(
     }
 }
 
-__global__ void init_state_kernel(EmbedState *st, double *hist, int nhist) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) {
+// Per instance: reset the loop state, fill the history with NaN, convert X0
+// to SoA (padding rows 0).  One workgroup per instance.
+__global__ void init_kernel(const InstDesc *__restrict__ insts, int nhist) {
+    const InstDesc &b = insts[blockIdx.x];
+    const TriGeom &g = b.g;
+    const int D = b.D;
+    if (threadIdx.x == 0) {
+        EmbedState *st = b.st;
         st->done = 0;
         st->iters_run = 0;
         st->converged = 0;
@@ -537,7 +544,30 @@ __global__ void init_state_kernel(EmbedState *st, double *hist, int nhist) {
         st->last = 0.0;
         st->sigma = st->fid = st->com = 0.0;
     }
-    if (i < nhist) hist[i] = __builtin_nan("");
+    if (b.hist)
+        for (int q = threadIdx.x; q < nhist; q += blockDim.x) b.hist[q] = __builtin_nan("");
+    const int tot = g.m * g.npad;
+    for (int q = threadIdx.x; q < tot; q += blockDim.x) {
+        const int a = q / g.npad, j = q - a * g.npad;
+        for (int k = 0; k < D; ++k)
+            b.Xs[0][((size_t)a * D + k) * g.npad + j] =
+                (j < g.n) ? b.X[((size_t)a * g.n + j) * D + k] : 0.f;
+    }
+}
+
+// Per instance: write the returned configuration X_{iters_run} back to the
+// caller's AoS buffer.
+__global__ void copy_out_kernel(const InstDesc *__restrict__ insts) {
+    const InstDesc &b = insts[blockIdx.x];
+    const TriGeom &g = b.g;
+    const int D = b.D;
+    const float *Xs = b.Xs[b.st->iters_run & 1];
+    const int tot = g.m * g.n;
+    for (int q = threadIdx.x; q < tot; q += blockDim.x) {
+        const int a = q / g.n, j = q - a * g.n;
+        for (int k = 0; k < D; ++k)
+            b.X[((size_t)a * g.n + j) * D + k] = Xs[((size_t)a * D + k) * g.npad + j];
+    }
 }
 
 __global__ void to_soa_kernel(TriGeom g, int D, const float *__restrict__ X,
@@ -550,123 +580,92 @@ __global__ void to_soa_kernel(TriGeom g, int D, const float *__restrict__ X,
             (j < g.n) ? X[((size_t)a * g.n + j) * D + k] : 0.f;
 }
 
-__global__ void from_soa_kernel(TriGeom g, int D, const float *__restrict__ Xa,
-                                const float *__restrict__ Xb,
-                                const EmbedState *__restrict__ st,
-                                float *__restrict__ X) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    const int a = idx / g.n, j = idx - a * g.n;
-    if (a >= g.m) return;
-    const float *Xs = (st->iters_run & 1) ? Xb : Xa;
-    for (int k = 0; k < D; ++k)
-        X[((size_t)a * g.n + j) * D + k] = Xs[((size_t)a * D + k) * g.npad + j];
-}
-
 template <int D, int CPL, int G, bool DBUF, bool VEC4>
-hipError_t launch_bx_t(const TriGeom &g, const DeltaPtrs &dp, const float *Xs,
-                       const uint32_t *tiles, float *P, double *F,
-                       const EmbedState *st, bool stress, bool acc,
-                       hipStream_t s) {
-    const unsigned nb = (unsigned)(g.m * (g.nint + g.nbnd));
-    if (nb == 0) return hipSuccess;
-    const dim3 grid(nb), block(WAVE);
+hipError_t launch_stream_t(const InstDesc *insts, const StreamItem *items, int nitems,
+                           int cur, bool stress, bool acc, hipStream_t s) {
+    if (nitems == 0) return hipSuccess;
+    const dim3 grid((unsigned)nitems), block(WAVE);
     if (stress && acc)
-        bx_kernel<D, CPL, G, DBUF, VEC4, true, true><<<grid, block, 0, s>>>(g, dp, Xs, tiles, P, F, st);
+        bx_kernel<D, CPL, G, DBUF, VEC4, true, true><<<grid, block, 0, s>>>(insts, items, cur);
     else if (acc)
-        bx_kernel<D, CPL, G, DBUF, VEC4, false, true><<<grid, block, 0, s>>>(g, dp, Xs, tiles, P, F, st);
+        bx_kernel<D, CPL, G, DBUF, VEC4, false, true><<<grid, block, 0, s>>>(insts, items, cur);
     else
-        bx_kernel<D, CPL, G, DBUF, VEC4, true, false><<<grid, block, 0, s>>>(g, dp, Xs, tiles, P, F, st);
+        bx_kernel<D, CPL, G, DBUF, VEC4, true, false><<<grid, block, 0, s>>>(insts, items, cur);
     return hipGetLastError();
 }
 
-// Kernel variants: (columns per lane, rows per group, double-buffered rows).
 template <int D, int CPL, int G, bool DBUF>
-hipError_t launch_bx_v(const TriGeom &g, const DeltaPtrs &dp, const float *Xs,
-                       const uint32_t *tiles, float *P, double *F,
-                       const EmbedState *st, bool stress, bool acc,
-                       hipStream_t s) {
-    return g.vec4 ? launch_bx_t<D, CPL, G, DBUF, true>(g, dp, Xs, tiles, P, F, st, stress, acc, s)
-                  : launch_bx_t<D, CPL, G, DBUF, false>(g, dp, Xs, tiles, P, F, st, stress, acc, s);
+hipError_t launch_stream_v(int vec4, const InstDesc *insts, const StreamItem *items,
+                           int nitems, int cur, bool stress, bool acc, hipStream_t s) {
+    return vec4 ? launch_stream_t<D, CPL, G, DBUF, true>(insts, items, nitems, cur, stress, acc, s)
+                : launch_stream_t<D, CPL, G, DBUF, false>(insts, items, nitems, cur, stress, acc, s);
 }
 
+// Kernel variants (columns per lane, rows per group, double-buffered rows);
+// the numbering is shared with the host's variant table.
 template <int D>
-hipError_t launch_bx_d(const TriGeom &g, const DeltaPtrs &dp, const float *Xs,
-                       const uint32_t *tiles, float *P, double *F,
-                       const EmbedState *st, bool stress, bool acc,
-                       hipStream_t s) {
-    switch (g.variant) {
-    case 1: return launch_bx_v<D, 4, 8, false>(g, dp, Xs, tiles, P, F, st, stress, acc, s);
-    case 2: return launch_bx_v<D, 4, 4, true>(g, dp, Xs, tiles, P, F, st, stress, acc, s);
-    case 3: return launch_bx_v<D, 8, 4, true>(g, dp, Xs, tiles, P, F, st, stress, acc, s);
-    case 4: return launch_bx_v<D, 8, 4, false>(g, dp, Xs, tiles, P, F, st, stress, acc, s);
-    case 5: return launch_bx_v<D, 8, 8, false>(g, dp, Xs, tiles, P, F, st, stress, acc, s);
-    default: return launch_bx_v<D, 4, 8, true>(g, dp, Xs, tiles, P, F, st, stress, acc, s);
+hipError_t launch_stream_d(int variant, int vec4, const InstDesc *insts,
+                           const StreamItem *items, int nitems, int cur, bool stress,
+                           bool acc, hipStream_t s) {
+    switch (variant) {
+    case 1: return launch_stream_v<D, 4, 8, false>(vec4, insts, items, nitems, cur, stress, acc, s);
+    case 2: return launch_stream_v<D, 8, 4, false>(vec4, insts, items, nitems, cur, stress, acc, s);
+    case 3: return launch_stream_v<D, 8, 8, false>(vec4, insts, items, nitems, cur, stress, acc, s);
+    default: return launch_stream_v<D, 4, 8, true>(vec4, insts, items, nitems, cur, stress, acc, s);
     }
 }
 
 }  // namespace
 
-hipError_t launch_bx(const TriGeom &g, int D, const DeltaPtrs &dp,
-                     const float *Xs, const uint32_t *tiles, float *P,
-                     double *F, const EmbedState *st, bool stress, bool acc,
-                     hipStream_t s) {
+hipError_t launch_stream(int D, int variant, int vec4, const InstDesc *insts,
+                         const StreamItem *items, int nitems, int cur, bool stress,
+                         bool acc, hipStream_t s) {
     switch (D) {
-    case 1: return launch_bx_d<1>(g, dp, Xs, tiles, P, F, st, stress, acc, s);
-    case 2: return launch_bx_d<2>(g, dp, Xs, tiles, P, F, st, stress, acc, s);
-    case 3: return launch_bx_d<3>(g, dp, Xs, tiles, P, F, st, stress, acc, s);
-    case 4: return launch_bx_d<4>(g, dp, Xs, tiles, P, F, st, stress, acc, s);
-    case 5: return launch_bx_d<5>(g, dp, Xs, tiles, P, F, st, stress, acc, s);
-    case 6: return launch_bx_d<6>(g, dp, Xs, tiles, P, F, st, stress, acc, s);
-    case 7: return launch_bx_d<7>(g, dp, Xs, tiles, P, F, st, stress, acc, s);
-    case 8: return launch_bx_d<8>(g, dp, Xs, tiles, P, F, st, stress, acc, s);
+    case 1: return launch_stream_d<1>(variant, vec4, insts, items, nitems, cur, stress, acc, s);
+    case 2: return launch_stream_d<2>(variant, vec4, insts, items, nitems, cur, stress, acc, s);
+    case 3: return launch_stream_d<3>(variant, vec4, insts, items, nitems, cur, stress, acc, s);
+    case 4: return launch_stream_d<4>(variant, vec4, insts, items, nitems, cur, stress, acc, s);
+    case 5: return launch_stream_d<5>(variant, vec4, insts, items, nitems, cur, stress, acc, s);
+    case 6: return launch_stream_d<6>(variant, vec4, insts, items, nitems, cur, stress, acc, s);
+    case 7: return launch_stream_d<7>(variant, vec4, insts, items, nitems, cur, stress, acc, s);
+    case 8: return launch_stream_d<8>(variant, vec4, insts, items, nitems, cur, stress, acc, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-// Number of commensurability partials the finalize / com kernels write.
-int finalize_blocks(const TriGeom &g, int D) { return (g.npad + FIN_BLOCK - 1) / FIN_BLOCK * D; }
-
-hipError_t launch_finalize(const TriGeom &g, int D, const float *P,
-                           const double *Winv, const double *wmat,
-                           float *Xout, double *comP, int ncomblk,
-                           const EmbedState *st, bool want_com,
-                           hipStream_t s) {
-    const dim3 grid((unsigned)((g.npad + FIN_BLOCK - 1) / FIN_BLOCK), (unsigned)D), block(FIN_BLOCK);
-    (void)ncomblk;
-    if (g.m <= 4)
-        finalize_kernel<4><<<grid, block, 0, s>>>(g, D, P, Winv, wmat, Xout, comP, st, want_com);
-    else if (g.m <= 8)
-        finalize_kernel<8><<<grid, block, 0, s>>>(g, D, P, Winv, wmat, Xout, comP, st, want_com);
+hipError_t launch_finalize(int maxm, const InstDesc *insts, const RowItem *rows, int nrows,
+                           int cur, bool want_com, hipStream_t s) {
+    if (nrows == 0) return hipSuccess;
+    const dim3 grid((unsigned)nrows), block(FIN_ROWS);
+    if (maxm <= 4)
+        finalize_kernel<4><<<grid, block, 0, s>>>(insts, rows, cur, want_com);
+    else if (maxm <= 8)
+        finalize_kernel<8><<<grid, block, 0, s>>>(insts, rows, cur, want_com);
     else
-        finalize_kernel<MAXM><<<grid, block, 0, s>>>(g, D, P, Winv, wmat, Xout, comP, st, want_com);
+        finalize_kernel<MAXM><<<grid, block, 0, s>>>(insts, rows, cur, want_com);
     return hipGetLastError();
 }
 
-hipError_t launch_com(const TriGeom &g, int D, const float *Xs,
-                      const double *wmat, double *comP, int ncomblk,
-                      hipStream_t s) {
-    (void)ncomblk;
-    com_kernel<<<dim3((unsigned)((g.npad + FIN_BLOCK - 1) / FIN_BLOCK), (unsigned)D),
-                 dim3(FIN_BLOCK), 0, s>>>(g, D, Xs, wmat, comP);
+hipError_t launch_com(const InstDesc *insts, const RowItem *rows, int nrows, hipStream_t s) {
+    if (nrows == 0) return hipSuccess;
+    com_kernel<<<dim3((unsigned)nrows), dim3(FIN_ROWS), 0, s>>>(insts, rows);
     return hipGetLastError();
 }
 
-hipError_t launch_reduce(const TriGeom &g, const double *F,
-                         const double *wmat, const double *comP, int ncomblk,
-                         EmbedState *st, double *hist, int t, int check,
-                         int final_pass, int iters, double tol, int tol_mode,
-                         hipStream_t s) {
-    const double mn = (double)g.m * g.n;
-    reduce_kernel<<<1, RED_BLOCK, 0, s>>>(g.m, g.nint + g.nbnd, F, wmat, comP, ncomblk,
-                                          st, hist, t, check, final_pass, iters,
-                                          tol, tol_mode, 0.5 * mn * (mn - 1.0));
+hipError_t launch_reduce(const InstDesc *insts, int count, int t, int check, int final_pass,
+                         int iters, double tol, int tol_mode, hipStream_t s) {
+    reduce_kernel<<<(unsigned)count, RED_BLOCK, 0, s>>>(insts, t, check, final_pass, iters,
+                                                        tol, tol_mode);
     return hipGetLastError();
 }
 
-hipError_t launch_init_state(EmbedState *st, double *hist, int nhist,
-                             hipStream_t s) {
-    const int nb = (nhist + 255) / 256;
-    init_state_kernel<<<nb > 0 ? nb : 1, 256, 0, s>>>(st, hist, nhist);
+hipError_t launch_init(const InstDesc *insts, int count, int nhist, hipStream_t s) {
+    init_kernel<<<(unsigned)count, 256, 0, s>>>(insts, nhist);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_out(const InstDesc *insts, int count, hipStream_t s) {
+    copy_out_kernel<<<(unsigned)count, 256, 0, s>>>(insts);
     return hipGetLastError();
 }
 
@@ -674,14 +673,6 @@ hipError_t launch_to_soa(const TriGeom &g, int D, const float *X, float *Xs,
                          hipStream_t s) {
     const size_t tot = (size_t)g.m * g.npad;
     to_soa_kernel<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(g, D, X, Xs);
-    return hipGetLastError();
-}
-
-hipError_t launch_from_soa(const TriGeom &g, int D, const float *Xa,
-                           const float *Xb, const EmbedState *st, float *X,
-                           hipStream_t s) {
-    const size_t tot = (size_t)g.m * g.n;
-    from_soa_kernel<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(g, D, Xa, Xb, st, X);
     return hipGetLastError();
 }
 

@@ -23,7 +23,8 @@ FJOFC_MAX_D = 8
 # Every symbol include/fjofc.h declares.
 EXPORTS = ["fjofc_create", "fjofc_destroy", "fjofc_last_error", "fjofc_strerror",
            "fjofc_embed", "fjofc_embed_w", "fjofc_stress", "fjofc_oos",
-           "fjofc_profile_enable", "fjofc_profile_read"]
+           "fjofc_profile_enable", "fjofc_profile_read", "fjofc_batch_create",
+           "fjofc_batch_run", "fjofc_batch_destroy", "fjofc_embed_batched"]
 
 
 class FjofcResult(C.Structure):
@@ -42,10 +43,17 @@ class FjofcProfile(C.Structure):
                 ("finalize_launches", C.c_int), ("finalize_ms", C.c_double),
                 ("reduce_launches", C.c_int), ("reduce_ms", C.c_double),
                 ("oos_launches", C.c_int), ("oos_ms", C.c_double),
-                ("oos_bytes", C.c_double)]
+                ("oos_bytes", C.c_double), ("batch_launches", C.c_int),
+                ("batch_ms", C.c_double), ("batch_bytes", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class FjofcProblem(C.Structure):
+    _fields_ = [("m", C.c_int), ("n", C.c_int), ("d", C.c_int),
+                ("delta", C.POINTER(C.c_void_p)), ("wmat", C.POINTER(C.c_double)),
+                ("X", C.c_void_p)]
 
 
 class FjofcError(RuntimeError):
@@ -82,6 +90,12 @@ def lib():
                                    C.POINTER(FjofcResult), vp]
         L.fjofc_oos.argtypes = [vp, vp, ip, ip, ip, C.POINTER(dp), vp, ip, vp,
                                 ip, dp, vp, vp, vp, ip, vp]
+        L.fjofc_batch_create.argtypes = [vp, C.POINTER(FjofcProblem), ip, C.POINTER(vp)]
+        L.fjofc_batch_run.argtypes = [vp, ip, dp, ip, ip, C.POINTER(FjofcResult), vp]
+        L.fjofc_batch_destroy.argtypes = [vp]
+        L.fjofc_batch_destroy.restype = None
+        L.fjofc_embed_batched.argtypes = [vp, C.POINTER(FjofcProblem), ip, ip, dp, ip, ip,
+                                          C.POINTER(FjofcResult), vp]
         L.fjofc_profile_enable.argtypes = [vp, ip]
         L.fjofc_profile_read.argtypes = [vp, C.POINTER(FjofcProfile)]
         _lib = L
@@ -202,3 +216,70 @@ def fjofc_profile_read(ctx: Context) -> dict:
     p = FjofcProfile()
     _check(lib().fjofc_profile_read(ctx.handle, C.byref(p)))
     return p.as_dict()
+
+
+class Batch:
+    """A planned batch of independent in-sample problems (fjofc_batch).
+
+    problems: sequence of (delta list, wmat, X) with CUDA float32 tensors;
+    the tensors are referenced, not copied, and must outlive the plan."""
+
+    def __init__(self, ctx: Context, problems):
+        import torch
+        self.ctx = ctx
+        self._keep = []
+        arr = (FjofcProblem * len(problems))()
+        for p, (delta, wmat, X) in enumerate(problems):
+            m = len(delta)
+            ptrs = (C.c_void_p * m)(*[_dev_ptr(t, torch.float32, "delta") for t in delta])
+            w, wp = _wmat_arg(wmat, m)
+            self._keep += [ptrs, w]
+            arr[p] = FjofcProblem(m, int(delta[0].shape[0]), int(X.shape[1]),
+                                  C.cast(ptrs, C.POINTER(C.c_void_p)), wp,
+                                  _dev_ptr(X, torch.float32, "X"))
+        self._arr = arr
+        self.count = len(problems)
+        self._h = C.c_void_p()
+        _check(lib().fjofc_batch_create(ctx.handle, arr, self.count, C.byref(self._h)))
+
+    def run(self, iters: int, tol: float = 0.0, tol_mode: int = FJOFC_TOL_REL,
+            stress_every: int = 1, want_results: bool = True, stream=None):
+        res = (FjofcResult * self.count)() if want_results else None
+        _check(lib().fjofc_batch_run(self._h, int(iters), float(tol), int(tol_mode),
+                                     int(stress_every), res, _stream_ptr(stream)))
+        return [r.as_dict() for r in res] if want_results else None
+
+    def close(self):
+        if self._h:
+            lib().fjofc_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fjofc_batch_create(ctx: Context, problems) -> Batch:
+    return Batch(ctx, problems)
+
+
+def fjofc_batch_run(batch: Batch, iters: int, **kw):
+    return batch.run(iters, **kw)
+
+
+def fjofc_batch_destroy(batch: Batch):
+    batch.close()
+
+
+def fjofc_embed_batched(ctx: Context, problems, iters: int, tol: float = 0.0,
+                        tol_mode: int = FJOFC_TOL_REL, stress_every: int = 1,
+                        stream=None):
+    """Plan, run and release a batch in one call; returns the results."""
+    b = Batch(ctx, problems)
+    try:
+        return b.run(iters, tol=tol, tol_mode=tol_mode, stress_every=stress_every,
+                     stream=stream)
+    finally:
+        b.close()
