@@ -189,6 +189,53 @@ int fjofc_embed_batched(fjofc_ctx *ctx, const fjofc_problem *probs, int count,
                         fjofc_result *res, void *stream);
 
 /*
+ * Learned warm start for out-of-sample embedding: a multilayer perceptron
+ * mapping a new object's dissimilarities to a fixed set of in-sample
+ * landmark objects (all modalities) to a starting point for the Section 3
+ * iteration, refined there by Guttman transforms (which also judge it).
+ * Layers l = 0..L-1: z = h W_l + b_l (W_l is dims[l] x dims[l+1],
+ * row-major), h' = GELU(z) = z Phi(z) after every layer but the last.
+ * Products run on BF16 matrix cores with FP32 accumulation: FP32 master
+ * weights with BF16 copies; activations and the backward gradients used as
+ * product operands are BF16 (round to nearest even); everything else FP32.
+ * Loss: mean squared error.  Optimiser: Adam with bias correction.
+ * All array arguments are device memory; calls enqueue on `stream`.
+ */
+typedef struct fjofc_mlp fjofc_mlp;
+
+/* dims: L + 1 widths; max_batch: rows per call.  On the current device.   */
+int fjofc_mlp_create(fjofc_ctx *ctx, int L, const int *dims, int max_batch,
+                     fjofc_mlp **out);
+void fjofc_mlp_destroy(fjofc_mlp *net);
+/* Copy FP32 parameters in (W[l], b[l] device arrays); resets Adam.         */
+int fjofc_mlp_set_params(fjofc_mlp *net, const float *const *W,
+                         const float *const *b, void *stream);
+int fjofc_mlp_get_params(fjofc_mlp *net, float *const *W, float *const *b,
+                         void *stream);
+/* out (B x dims[L] FP32) = network(x), x: B x dims[0] BF16 (uint16 bits). */
+int fjofc_mlp_forward(fjofc_mlp *net, const unsigned short *x, int B,
+                      float *out, void *stream);
+/* Warm start for fjofc_oos: Y (B x m x dims[L] FP32) receives the
+ * network's point for every one of the object's m modalities.            */
+int fjofc_mlp_predict_start(fjofc_mlp *net, const unsigned short *x, int B,
+                            int m, float *Y, void *stream);
+/* Forward, MSE against y (B x dims[L] FP32), backward: the gradients are
+ * kept in the network (fjofc_mlp_get_grads); loss (optional, FP64).      */
+int fjofc_mlp_backward(fjofc_mlp *net, const unsigned short *x, const float *y,
+                       int B, double *loss, void *stream);
+int fjofc_mlp_get_grads(fjofc_mlp *net, float *const *dW, float *const *db,
+                        void *stream);
+/* One Adam step with the stored gradients (FP32 masters, BF16 refreshed). */
+int fjofc_mlp_adam(fjofc_mlp *net, float lr, float beta1, float beta2,
+                   float eps, void *stream);
+/* Features of k new objects: x[o][i*L + l] = BF16((delta_new[o][i][lm[l]]
+ * - mu[i*L + l]) * inv_sd[i*L + l]); delta_new is k x m x n FP32 (as for
+ * fjofc_oos), landmarks L int32 indices in [0, n) (clamped).              */
+int fjofc_mlp_features(fjofc_ctx *ctx, const float *delta_new, int k, int m,
+                       int n, const int *landmarks, int L, const float *mu,
+                       const float *inv_sd, unsigned short *x, void *stream);
+
+/*
  * Per-kernel timing (tracing aid).  While enabled, every kernel launch of
  * fjofc_embed / fjofc_stress / fjofc_oos is bracketed by HIP events on the
  * caller's stream; fjofc_profile_read synchronises and returns the summed

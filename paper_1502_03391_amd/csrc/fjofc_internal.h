@@ -130,4 +130,29 @@ struct OOSArgs {
 // colsum: workspace of m * D doubles (sum_j X^(i)_j, computed first).
 hipError_t launch_oos(const OOSArgs &a, double *colsum, hipStream_t s);
 
+// ---- warm-start network (mlp.hip) -------------------------------------
+enum { GEMM_HIDDEN = 0, GEMM_LAST = 1, GEMM_BWD = 2, GEMM_STORE = 3 };
+struct GemmEpi {
+    const float *bias;  // HIDDEN, LAST
+    float *outf;        // Z (HIDDEN), output (LAST), g (BWD), C (STORE)
+    uint16_t *outb;     // BF16 GELU(Z) (HIDDEN), BF16 g (BWD)
+    const float *Z;     // pre-activations (BWD)
+    long ldc;
+};
+hipError_t launch_gemm(int epi, int M, int N, int K, const uint16_t *A, long sam, long sak,
+                       const uint16_t *B, long sbk, long sbn, const GemmEpi &e, hipStream_t s);
+hipError_t launch_mse(const float *out, const float *y, int B, int k, float *G, uint16_t *Gb,
+                      double *loss, hipStream_t s);
+hipError_t launch_colsum(const float *G, int B, int N, float *db, hipStream_t s);
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, uint16_t *p16, long n,
+                       float lr, float b1, float b2, float eps, float c1, float c2,
+                       hipStream_t s);
+hipError_t launch_to_bf16(const float *x, uint16_t *y, long n, hipStream_t s);
+hipError_t launch_broadcast(const float *out, int B, int m, int d, float *Y, hipStream_t s);
+hipError_t launch_features(const float *dnew, int k, int m, int n, const int *lm, int L,
+                           const float *mu, const float *isd, uint16_t *x, hipStream_t s);
+
+// Records the calling thread's error message (host.cpp); returns `code`.
+int set_error(int code, const char *fmt, ...);
+
 }  // namespace fjofc

@@ -525,6 +525,16 @@ int run_insample(fjofc_ctx *ctx, const float *const *delta, int m, int n,
 
 }  // namespace
 
+int fjofc::set_error(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
 // A batch of independent in-sample problems advanced in lockstep; the whole
 // loop is captured once into a HIP graph on a library-owned stream and
 // replayed by every fjofc_batch_run with the same loop parameters.

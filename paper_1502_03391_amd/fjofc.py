@@ -24,7 +24,11 @@ FJOFC_MAX_D = 8
 EXPORTS = ["fjofc_create", "fjofc_destroy", "fjofc_last_error", "fjofc_strerror",
            "fjofc_embed", "fjofc_embed_w", "fjofc_stress", "fjofc_oos",
            "fjofc_profile_enable", "fjofc_profile_read", "fjofc_batch_create",
-           "fjofc_batch_run", "fjofc_batch_destroy", "fjofc_embed_batched"]
+           "fjofc_batch_run", "fjofc_batch_destroy", "fjofc_embed_batched",
+           "fjofc_mlp_create", "fjofc_mlp_destroy", "fjofc_mlp_set_params",
+           "fjofc_mlp_get_params", "fjofc_mlp_forward", "fjofc_mlp_backward",
+           "fjofc_mlp_get_grads", "fjofc_mlp_adam", "fjofc_mlp_features",
+           "fjofc_mlp_predict_start"]
 
 
 class FjofcResult(C.Structure):
@@ -72,6 +76,9 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python paper_1502_03391_amd/build.py`")
+        # libfjofc and PyTorch link the same HIP runtime soname; loading
+        # torch first makes the process use one runtime (torch's) for both.
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         vp, ip, dp = C.c_void_p, C.c_int, C.c_double
         L.fjofc_create.argtypes = [C.POINTER(vp), ip]
@@ -96,6 +103,17 @@ def lib():
         L.fjofc_batch_destroy.restype = None
         L.fjofc_embed_batched.argtypes = [vp, C.POINTER(FjofcProblem), ip, ip, dp, ip, ip,
                                           C.POINTER(FjofcResult), vp]
+        L.fjofc_mlp_create.argtypes = [vp, ip, C.POINTER(ip), ip, C.POINTER(vp)]
+        L.fjofc_mlp_destroy.argtypes = [vp]
+        L.fjofc_mlp_destroy.restype = None
+        L.fjofc_mlp_set_params.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), vp]
+        L.fjofc_mlp_get_params.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), vp]
+        L.fjofc_mlp_forward.argtypes = [vp, vp, ip, vp, vp]
+        L.fjofc_mlp_backward.argtypes = [vp, vp, vp, ip, vp, vp]
+        L.fjofc_mlp_predict_start.argtypes = [vp, vp, ip, ip, vp, vp]
+        L.fjofc_mlp_get_grads.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), vp]
+        L.fjofc_mlp_adam.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float, vp]
+        L.fjofc_mlp_features.argtypes = [vp, vp, ip, ip, ip, vp, ip, vp, vp, vp, vp]
         L.fjofc_profile_enable.argtypes = [vp, ip]
         L.fjofc_profile_read.argtypes = [vp, C.POINTER(FjofcProfile)]
         _lib = L
@@ -283,3 +301,97 @@ def fjofc_embed_batched(ctx: Context, problems, iters: int, tol: float = 0.0,
                      stream=stream)
     finally:
         b.close()
+
+
+class Mlp:
+    """Warm-start network (fjofc_mlp): dims = [in, hidden..., out]."""
+
+    def __init__(self, ctx: Context, dims, max_batch: int):
+        self.ctx = ctx
+        self.dims = [int(x) for x in dims]
+        self.L = len(self.dims) - 1
+        self.max_batch = int(max_batch)
+        self._h = C.c_void_p()
+        arr = (C.c_int * len(self.dims))(*self.dims)
+        _check(lib().fjofc_mlp_create(ctx.handle, self.L, arr, self.max_batch, C.byref(self._h)))
+
+    def _ptrs(self, tensors, dtype, name):
+        return (C.c_void_p * self.L)(*[_dev_ptr(t, dtype, name) for t in tensors])
+
+    def set_params(self, W, b, stream=None):
+        import torch
+        _check(lib().fjofc_mlp_set_params(self._h, self._ptrs(W, torch.float32, "W"),
+                                          self._ptrs(b, torch.float32, "b"), _stream_ptr(stream)))
+
+    def get_params(self, stream=None):
+        import torch
+        W = [torch.empty((a, c), dtype=torch.float32, device="cuda")
+             for a, c in zip(self.dims[:-1], self.dims[1:])]
+        b = [torch.empty(c, dtype=torch.float32, device="cuda") for c in self.dims[1:]]
+        _check(lib().fjofc_mlp_get_params(self._h, self._ptrs(W, torch.float32, "W"),
+                                          self._ptrs(b, torch.float32, "b"), _stream_ptr(stream)))
+        return W, b
+
+    def forward(self, x, out=None, stream=None):
+        import torch
+        B = int(x.shape[0])
+        if out is None:
+            out = torch.empty((B, self.dims[-1]), dtype=torch.float32, device="cuda")
+        _check(lib().fjofc_mlp_forward(self._h, _dev_ptr(x, torch.bfloat16, "x"), B,
+                                       _dev_ptr(out, torch.float32, "out"), _stream_ptr(stream)))
+        return out
+
+    def predict_start(self, x, m, Y, stream=None):
+        """Y (B x m x dims[-1]) = the network's point for every modality."""
+        import torch
+        _check(lib().fjofc_mlp_predict_start(self._h, _dev_ptr(x, torch.bfloat16, "x"),
+                                             int(x.shape[0]), int(m),
+                                             _dev_ptr(Y, torch.float32, "Y"), _stream_ptr(stream)))
+        return Y
+
+    def backward(self, x, y, loss=None, stream=None):
+        import torch
+        lp = _dev_ptr(loss, torch.float64, "loss") if loss is not None else None
+        _check(lib().fjofc_mlp_backward(self._h, _dev_ptr(x, torch.bfloat16, "x"),
+                                        _dev_ptr(y, torch.float32, "y"), int(x.shape[0]), lp,
+                                        _stream_ptr(stream)))
+
+    def get_grads(self, stream=None):
+        import torch
+        dW = [torch.empty((a, c), dtype=torch.float32, device="cuda")
+              for a, c in zip(self.dims[:-1], self.dims[1:])]
+        db = [torch.empty(c, dtype=torch.float32, device="cuda") for c in self.dims[1:]]
+        _check(lib().fjofc_mlp_get_grads(self._h, self._ptrs(dW, torch.float32, "dW"),
+                                         self._ptrs(db, torch.float32, "db"), _stream_ptr(stream)))
+        return dW, db
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        _check(lib().fjofc_mlp_adam(self._h, float(lr), float(beta1), float(beta2), float(eps),
+                                    _stream_ptr(stream)))
+
+    def close(self):
+        if self._h:
+            lib().fjofc_mlp_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fjofc_mlp_features(ctx: Context, delta_new, landmarks, mu, inv_sd, x, stream=None):
+    """x (k x m L, bfloat16) = standardised dissimilarities to the landmarks."""
+    import torch
+    k, m, n = (int(s) for s in delta_new.shape)
+    L = int(landmarks.shape[0])
+    lm = landmarks.detach()
+    if int(lm.min()) < 0 or int(lm.max()) >= n:
+        raise ValueError("landmark index out of range")
+    _check(lib().fjofc_mlp_features(ctx.handle, _dev_ptr(delta_new, torch.float32, "delta_new"),
+                                    k, m, n, _dev_ptr(lm, torch.int32, "landmarks"), L,
+                                    _dev_ptr(mu, torch.float32, "mu"),
+                                    _dev_ptr(inv_sd, torch.float32, "inv_sd"),
+                                    _dev_ptr(x, torch.bfloat16, "x"), _stream_ptr(stream)))
+    return x

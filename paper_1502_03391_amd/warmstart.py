@@ -1,0 +1,278 @@
+"""Learned warm start for out-of-sample fJOFC (all GPU work through libfjofc).
+
+Pipeline (every numerical step runs in the library's kernels; torch holds
+device memory and does index plumbing):
+
+1. In-sample embedding X of n objects in m modalities (fjofc_embed).
+2. Training pairs: new objects from the same latent model, their
+   dissimilarities to all in-sample objects, out-of-sample transforms from a
+   plain random start (fjofc_oos); the target is the mean over modalities of
+   the converged points (one consensus point per object).
+3. Features: the dissimilarities to L fixed landmark objects in every
+   modality, standardised with training statistics (fjofc_mlp_features).
+4. Training: MSE, Adam, cosine learning rate (fjofc_mlp_backward / _adam).
+5. Evaluation on held-out objects: the plain start runs `iters` transforms
+   and defines each object's reference stress; the warm start (network
+   point for every modality, fjofc_mlp_predict_start) and a
+   nearest-in-sample start run until their stress is within `rel` of the
+   reference (fjofc_oos target), and iterations and wall time are reported.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+from . import fjofc
+
+
+@dataclass
+class WarmStartConfig:
+    landmarks: int = 256
+    hidden: int = 512
+    depth: int = 3            # hidden layers
+    train_objects: int = 200000
+    val_frac: float = 0.05
+    epochs: int = 20
+    batch: int = 1024
+    lr: float = 1e-3
+    oos_iters: int = 100
+    oos_batch: int = 4096
+    chunk: int = 20000
+    rel: float = 1e-4
+    seed_landmarks: int = 22
+    seed_train: int = 21
+    seed_eval: int = 20
+    seed_start: int = 23
+    seed_init: int = 24
+
+
+class Problem:
+    """In-sample side: views, maps, weights and the embedded X (device)."""
+
+    def __init__(self, ctx, spec, device):
+        import torch
+        from workloads import generators as gen
+        self.spec = spec
+        self.device = device
+        self.views, self.maps, X0 = gen.latent_views(spec.seed_in, spec.n, spec.m, spec.lat,
+                                                     spec.sigma, spec.d)
+        delta = [gen.pairwise_dist_torch(Y, device) for Y in self.views]
+        self.wmat = gen.uniform_wmat(spec.m, spec.w)
+        self.X = torch.from_numpy(X0.astype(np.float32)).to(device)
+        self.in_result, _ = fjofc.fjofc_embed(ctx, delta, self.wmat, self.X, spec.in_iters,
+                                              stress_every=spec.in_iters)
+        del delta
+        self.scale = float(torch.sqrt((self.X.double() ** 2).mean()))
+
+    def new_delta(self, new_views, o0, o1, out=None):
+        """k x m x n FP32 dissimilarities of new objects o0..o1-1."""
+        import torch
+        from workloads import generators as gen
+        sp = self.spec
+        k = o1 - o0
+        if out is None:
+            out = torch.empty((k, sp.m, sp.n), dtype=torch.float32, device=self.device)
+        for i in range(sp.m):
+            out[:, i, :] = gen.cross_dist_torch(new_views[i][o0:o1], self.views[i], self.device)
+        return out
+
+    def plain_start(self, seed, k):
+        import torch
+        from workloads import generators as gen
+        sp = self.spec
+        return torch.from_numpy(gen.gaussian_start(seed, (k, sp.m, sp.d), self.scale)
+                                .astype(np.float32)).to(self.device)
+
+
+def _run_oos(ctx, prob, dnew, Y, iters, batch, target=None, stress=None, its=None):
+    k = dnew.shape[0]
+    for o0 in range(0, k, batch):
+        o1 = min(k, o0 + batch)
+        fjofc.fjofc_oos(ctx, prob.X, prob.wmat, dnew[o0:o1], Y[o0:o1], iters,
+                        target=None if target is None else target[o0:o1],
+                        stress_out=None if stress is None else stress[o0:o1],
+                        iters_out=None if its is None else its[o0:o1], sync=False)
+
+
+def training_data(ctx, prob, cfg: WarmStartConfig, landmarks, log=print):
+    """Features (raw, FP32 for the statistics) and targets of the training
+    objects, generated chunk by chunk."""
+    import torch
+    from workloads import generators as gen
+    sp = prob.spec
+    new = gen.oos_objects(cfg.seed_train, cfg.train_objects, prob.maps, sp.sigma)
+    raw = torch.empty((cfg.train_objects, sp.m * cfg.landmarks), dtype=torch.float32,
+                      device=prob.device)
+    tgt = torch.empty((cfg.train_objects, sp.d), dtype=torch.float32, device=prob.device)
+    buf = None
+    lm = landmarks.long()
+    for o0 in range(0, cfg.train_objects, cfg.chunk):
+        o1 = min(cfg.train_objects, o0 + cfg.chunk)
+        buf = prob.new_delta(new, o0, o1, None if buf is None or buf.shape[0] != o1 - o0 else buf)
+        Y = prob.plain_start(cfg.seed_start + 1000 + o0, o1 - o0)
+        _run_oos(ctx, prob, buf, Y, cfg.oos_iters, cfg.oos_batch)
+        raw[o0:o1] = buf[:, :, lm].reshape(o1 - o0, -1)
+        tgt[o0:o1] = Y.mean(dim=1)
+        log(f"[warmstart] training data {o1}/{cfg.train_objects}")
+    torch.cuda.synchronize()
+    return raw, tgt
+
+
+def train_network(ctx, raw, tgt, cfg: WarmStartConfig, log=print):
+    """Standardise, split off a validation set, train with Adam and a cosine
+    learning rate.  Returns (net, mu, inv_sd, history)."""
+    import torch
+    N = raw.shape[0]
+    mu = raw.mean(0)
+    inv_sd = 1.0 / raw.std(0).clamp_min(1e-6)
+    dims = [raw.shape[1]] + [cfg.hidden] * cfg.depth + [tgt.shape[1]]
+    rng = np.random.default_rng(cfg.seed_init)
+    W = [torch.from_numpy((rng.standard_normal((a, b)) * math.sqrt(2.0 / a)).astype(np.float32))
+         .to(raw.device) for a, b in zip(dims[:-1], dims[1:])]
+    b = [torch.zeros(c, dtype=torch.float32, device=raw.device) for c in dims[1:]]
+    net = fjofc.Mlp(ctx, dims, cfg.batch)
+    net.set_params(W, b)
+    # standardise with the feature kernel: raw is N x m x L, landmarks 0..L-1
+    m = raw.shape[1] // cfg.landmarks
+    xs = torch.empty(raw.shape, dtype=torch.bfloat16, device=raw.device)
+    ident = torch.arange(cfg.landmarks, dtype=torch.int32, device=raw.device)
+    fjofc.fjofc_mlp_features(ctx, raw.view(N, m, cfg.landmarks), ident, mu.contiguous(),
+                             inv_sd.contiguous(), xs)
+    perm0 = torch.from_numpy(rng.permutation(N)).to(raw.device)
+    nval = int(N * cfg.val_frac)
+    val_idx, tr_idx = perm0[:nval], perm0[nval:]
+    ntr = tr_idx.shape[0]
+    steps_per_epoch = ntr // cfg.batch
+    total = steps_per_epoch * cfg.epochs
+    loss = torch.zeros(1, dtype=torch.float64, device=raw.device)
+    hist = []
+    step = 0
+    for ep in range(cfg.epochs):
+        order = tr_idx[torch.from_numpy(rng.permutation(ntr)).to(raw.device)]
+        xe, ye = xs[order], tgt[order]
+        acc = torch.zeros(1, dtype=torch.float64, device=raw.device)
+        for s in range(steps_per_epoch):
+            sl = slice(s * cfg.batch, (s + 1) * cfg.batch)
+            net.backward(xe[sl], ye[sl], loss)
+            lr = cfg.lr * 0.5 * (1.0 + math.cos(math.pi * step / max(1, total)))
+            net.adam(lr)
+            acc += loss
+            step += 1
+        vl = evaluate_loss(net, xs[val_idx], tgt[val_idx], cfg.batch)
+        hist.append({"epoch": ep, "train_mse": float(acc.item() / steps_per_epoch), "val_mse": vl})
+        log(f"[warmstart] epoch {ep}: train {hist[-1]['train_mse']:.4e} val {vl:.4e}")
+    return net, mu, inv_sd, hist
+
+
+def evaluate_loss(net, x, y, batch):
+    import torch
+    tot = 0.0
+    out = torch.empty((batch, y.shape[1]), dtype=torch.float32, device=x.device)
+    for o0 in range(0, x.shape[0], batch):
+        o1 = min(x.shape[0], o0 + batch)
+        o = net.forward(x[o0:o1], out[: o1 - o0])
+        tot += float(((o - y[o0:o1]) ** 2).sum())
+    return tot / (x.shape[0] * y.shape[1])
+
+
+def evaluate(ctx, prob, net, mu, inv_sd, landmarks, cfg: WarmStartConfig, k: int = 50000,
+             log=print):
+    """Plain start (reference), learned warm start and nearest-in-sample start
+    on k held-out objects: iterations and wall time to reach the plain
+    start's final stress within `rel`."""
+    import torch
+    from workloads import generators as gen
+    sp = prob.spec
+    dev = prob.device
+    new = gen.oos_objects(cfg.seed_eval, k, prob.maps, sp.sigma)
+    dnew = prob.new_delta(new, 0, k)
+    Y0 = prob.plain_start(cfg.seed_start, k)
+    torch.cuda.synchronize()
+
+    # plain start: the reference run
+    Yp = Y0.clone()
+    sp_stress = torch.empty(k, dtype=torch.float64, device=dev)
+    its_p = torch.empty(k, dtype=torch.int32, device=dev)
+    t0 = time.perf_counter()
+    _run_oos(ctx, prob, dnew, Yp, cfg.oos_iters, cfg.oos_batch, stress=sp_stress, its=its_p)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    target = sp_stress * (1.0 + cfg.rel)
+
+    def refine(Ystart, t_extra0):
+        st = torch.empty(k, dtype=torch.float64, device=dev)
+        it = torch.empty(k, dtype=torch.int32, device=dev)
+        _run_oos(ctx, prob, dnew, Ystart, cfg.oos_iters, cfg.oos_batch, target=target,
+                 stress=st, its=it)
+        torch.cuda.synchronize()
+        return st, it, time.perf_counter() - t_extra0
+
+    # learned warm start: features + network + refinement, timed together
+    x = torch.empty((k, sp.m * cfg.landmarks), dtype=torch.bfloat16, device=dev)
+    Yw = torch.empty((k, sp.m, sp.d), dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fjofc.fjofc_mlp_features(ctx, dnew, landmarks, mu, inv_sd, x)
+    for o0 in range(0, k, cfg.batch):
+        o1 = min(k, o0 + cfg.batch)
+        net.predict_start(x[o0:o1], sp.m, Yw[o0:o1])
+    st_w, it_w, t_warm = refine(Yw, t0)
+
+    # nearest-in-sample start (comparison): each modality's nearest in-sample
+    # object by dissimilarity
+    nn = dnew.argmin(dim=2)                                  # k x m
+    Xv = prob.X.view(sp.m, sp.n, sp.d)
+    Yn = torch.stack([Xv[i][nn[:, i]] for i in range(sp.m)], dim=1).contiguous()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st_n, it_n, t_nn = refine(Yn, t0)
+
+    def summ(st, it, t):
+        itn = it.cpu().numpy()
+        ok = (st <= target).cpu().numpy()
+        return {"seconds": t, "iters_mean": float(itn.mean()),
+                "iters_p50": float(np.percentile(itn, 50)),
+                "iters_p99": float(np.percentile(itn, 99)),
+                "reached_frac": float(ok.mean())}
+
+    res = {"objects": k, "rel": cfg.rel, "oos_iters_cap": cfg.oos_iters,
+           "plain": {"seconds": t_plain, "iters": cfg.oos_iters},
+           "warm": summ(st_w, it_w, t_warm),
+           "nearest": summ(st_n, it_n, t_nn)}
+    res["speedup_vs_plain"] = t_plain / res["warm"]["seconds"]
+    log(f"[warmstart] plain {t_plain:.3f}s; warm {res['warm']['seconds']:.3f}s "
+        f"(mean {res['warm']['iters_mean']:.1f} iters, reached {res['warm']['reached_frac']:.3f}); "
+        f"nearest {res['nearest']['seconds']:.3f}s (mean {res['nearest']['iters_mean']:.1f})")
+    return res
+
+
+def run(ctx, cfg: Optional[WarmStartConfig] = None, eval_objects: int = 50000, log=print,
+        spec=None):
+    """The whole learned warm-start workload; returns a summary dict.  `spec`
+    defaults to the out-of-sample workload (m=2, n=10000, d=5)."""
+    import torch
+    from workloads import generators as gen
+    cfg = cfg or WarmStartConfig()
+    spec = spec or gen.config2_spec()
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    prob = Problem(ctx, spec, dev)
+    rng = np.random.default_rng(cfg.seed_landmarks)
+    landmarks = torch.from_numpy(rng.choice(spec.n, cfg.landmarks, replace=False)
+                                 .astype(np.int32)).to(dev)
+    raw, tgt = training_data(ctx, prob, cfg, landmarks, log)
+    t1 = time.perf_counter()
+    net, mu, inv_sd, hist = train_network(ctx, raw, tgt, cfg, log)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    del raw, tgt
+    ev = evaluate(ctx, prob, net, mu, inv_sd, landmarks, cfg, eval_objects, log)
+    net.close()
+    return {"workload": f"warm_start_m{spec.m}_n{spec.n}_d{spec.d}",
+            "train_objects": cfg.train_objects,
+            "epochs": cfg.epochs, "data_seconds": t1 - t0, "train_seconds": t2 - t1,
+            "final_val_mse": hist[-1]["val_mse"], "eval": ev}
