@@ -1,16 +1,28 @@
 // Out-of-sample fast-JOFC kernel for gfx950 (Section 3).
 //
 // New objects carry no weight between one another, so the k out-of-sample
-// problems are independent; one workgroup owns a block of OB objects and
-// runs every Guttman transform of those objects itself (no grid-wide
-// synchronisation).  Each transform needs, per object o and modality i,
-//   r_j   = delta_oi(j) / ||X^(i)_j - y_oi||   (0 when the distance is 0)
-//   psi_i = w_ii sum_j r_j,   xi_i = w_ii (sum_j X^(i)_j - sum_j r_j X^(i)_j)
+// problems are independent.  One workgroup owns OB objects and runs every
+// Guttman transform of them itself.  Per object o and modality i a transform
+// needs, with r_j = delta_oi(j) / ||X^(i)_j - y_oi|| (eq:B's d = 0 rule:
+// the term vanishes),
+//   xi_i + psi_i y_oi = w_ii (sum_j X^(i)_j - sum_j r_j (X^(i)_j - y_oi)),
 // and then y_o <- L22^-1 (xi + diag(psi) y_o), L22 being the eq:modW matrix.
-// Threads own in-sample columns j (coalesced delta reads); each X^(i)_j is
-// loaded once per transform and reused for all OB objects of the block.
-// The out-of-sample stress (eq:joos) of the current y is formed in the same
-// pass, so the stop rules are tested on sigma(y_t) before y_{t+1} is made.
+// The kernel accumulates S_i = sum_j r_j (X^(i)_j - y_oi) directly (one FMA
+// per component instead of separate psi and sum r X, and no cancellation
+// between psi y and sum r X).  The out-of-sample stress (eq:joos) of the
+// current y is formed in the same pass, so the stop rules are tested on
+// sigma(y_t) before y_{t+1} is made.
+//
+// Layout: one workgroup of four waves owns four objects.  The 256 threads
+// split the in-sample index j (coalesced reads of each delta row); every
+// thread loads X^(i)_j once per transform and uses it for all live objects
+// of the block.  delta rows are read through buffer resources, so the ragged
+// end of a row costs no memory traffic.  Each wave reduces its partial sums
+// with a reduce-scatter (permlane swaps, DPP) into LDS; after a barrier,
+// wave c evaluates the stress, the stop rules and the FP64 update of the
+// block's c-th live object, and after a second barrier finished objects
+// leave the live list, so later transforms stream only live objects.  The
+// fidelity term is accumulated only on transforms whose stress is used.
 #include "fjofc_internal.h"
 #include <float.h>
 
@@ -20,158 +32,316 @@ namespace {
 constexpr int OOS_BLOCK = 256;
 constexpr int OOS_WAVES = OOS_BLOCK / WAVE;
 
-__device__ __forceinline__ float wave_sum_f(float v) {
-    const int lane = threadIdx.x & (WAVE - 1);
-#pragma unroll
-    for (int s = 32; s >= 1; s >>= 1)
-        v += __int_as_float(__builtin_amdgcn_ds_bpermute((lane ^ s) << 2, __float_as_int(v)));
-    return v;
+constexpr int DPP_QP_XOR1 = 0xB1;  // quad_perm [1,0,3,2]
+constexpr int DPP_QP_XOR2 = 0x4E;  // quad_perm [2,3,0,1]
+constexpr int DPP_ROW_HALF_MIRROR = 0x141;
+constexpr int DPP_ROW_ROR8 = 0x128;
+constexpr int BUF_DWORD3 = 0x00020000;  // raw 32-bit buffer, gfx9 family
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
 }
 
-template <int D, int OB>
-__global__ __launch_bounds__(OOS_BLOCK) void oos_kernel(
-    OOSArgs a, const double *__restrict__ colsum /* m x D */) {
-    constexpr int NV = D + 2;  // per (object, modality): psi, sum r X (D), fidelity
-    __shared__ float ys[OB][MAXM][D];
-    __shared__ float ynew[OB][MAXM][D];
-    __shared__ float red[OOS_WAVES][OB][NV];
-    __shared__ double acc[OB][MAXM][NV];
-    __shared__ int live[OB];
-    __shared__ double prev[OB];
-    __shared__ int any_live;
+// Lanes 0-31 return a summed over both 32-lane halves, lanes 32-63 return b.
+__device__ __forceinline__ float swap32_add(float a, float b) {
+    auto s = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(s[0]) + __uint_as_float(s[1]);
+}
+// Even 16-lane rows return a summed over the row pair, odd rows return b.
+__device__ __forceinline__ float swap16_add(float a, float b) {
+    auto s = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(s[0]) + __uint_as_float(s[1]);
+}
 
-    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
+// Reduce V values (V % 8 == 0) over the 64 lanes.  Afterwards c[r] in every
+// lane of an aligned group of 8 lanes holds the wave total of value
+//   r + bit3 V/8 + bit4 V/4 + bit5 V/2     (bits of the lane index).
+template <int V>
+__device__ __forceinline__ void reduce_scatter8(float (&p)[V], float (&c)[V / 8], int lane) {
+    static_assert(V % 8 == 0, "V is a multiple of 8");
+    float a[V / 2];
+#pragma unroll
+    for (int r = 0; r < V / 2; ++r) a[r] = swap32_add(p[r], p[r + V / 2]);
+    float b[V / 4];
+#pragma unroll
+    for (int r = 0; r < V / 4; ++r) b[r] = swap16_add(a[r], a[r + V / 4]);
+    const bool b3 = lane & 8;
+#pragma unroll
+    for (int r = 0; r < V / 8; ++r) {
+        const float send = b3 ? b[r] : b[r + V / 8];
+        const float keep = b3 ? b[r + V / 8] : b[r];
+        c[r] = keep + dpp<DPP_ROW_ROR8>(send);
+    }
+#pragma unroll
+    for (int r = 0; r < V / 8; ++r) {
+        c[r] += dpp<DPP_QP_XOR1>(c[r]);
+        c[r] += dpp<DPP_QP_XOR2>(c[r]);
+        c[r] += dpp<DPP_ROW_HALF_MIRROR>(c[r]);
+    }
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const float *p, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(p), (short)0, bytes, BUF_DWORD3);
+}
+
+// Per-pair work for the NL live slots.  FID adds the fidelity term
+// (delta - d)^2; MASK zeroes it for a lane past the row end (whose delta
+// reads as 0).
+template <int D, int NL, bool FID, bool MASK>
+__device__ __forceinline__ void pair_step(const float (&x)[D], const float (&dv)[NL],
+                                          const float (&yv)[NL][D], bool inside,
+                                          float (&s)[NL][D + 1]) {
+#pragma unroll
+    for (int o = 0; o < NL; ++o) {
+        float df[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) df[k] = x[k] - yv[o][k];
+        // d^2 floored at FLT_MIN: when the points coincide every df is 0, so
+        // the r df terms vanish (eq:B) while r stays finite.
+        float d2 = fmaf(df[0], df[0], FLT_MIN);
+#pragma unroll
+        for (int k = 1; k < D; ++k) d2 = fmaf(df[k], df[k], d2);
+        const float rs = __builtin_amdgcn_rsqf(d2);
+        const float r = dv[o] * rs;
+#pragma unroll
+        for (int k = 0; k < D; ++k) s[o][k] = fmaf(r, df[k], s[o][k]);
+        if (FID) {
+            float e = fmaf(-d2, rs, dv[o]);  // delta - d
+            if (MASK) e = inside ? e : 0.f;
+            s[o][D] = fmaf(e, e, s[o][D]);
+        }
+    }
+}
+
+// One modality's stream for the NL live slots: partial sums of S (and of
+// the fidelity when FID) over this thread's j, reduced over the wave and
+// written to dst (this wave's row of VP values for modality i; slot c's
+// values at c (D + 1)).  ord maps live position -> physical slot.
+template <int D, int NL, int U, bool FID>
+__device__ __forceinline__ void stream_modality(const OOSArgs &a, int i, int o0,
+                                                const int (&ord)[4], const float *ys,
+                                                float *dst, int tid) {
+    constexpr int NV = D + 1;
+    constexpr int VL = (NL * NV + 7) / 8 * 8;
     const int m = a.m, n = a.n, npad = a.npad;
+    const int lane = tid & (WAVE - 1);
+    float yv[NL][D];
+    __amdgpu_buffer_rsrc_t rs[NL];
+#pragma unroll
+    for (int o = 0; o < NL; ++o) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) yv[o][k] = ys[(ord[o] * m + i) * D + k];
+        rs[o] = row_rsrc(a.dnew + ((size_t)(o0 + ord[o]) * m + i) * n, n * 4);
+    }
+    // X^(i) components through one buffer resource: the lane offset j is
+    // shared by all D loads, the component offset is scalar.
+    const __amdgpu_buffer_rsrc_t xr = row_rsrc(a.Xs + (size_t)i * D * npad, D * npad * 4);
+    float s[NL][NV];
+#pragma unroll
+    for (int o = 0; o < NL; ++o)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) s[o][v] = 0.f;
+    // Full U-steps (every j inside the row) are software-pipelined over two
+    // register buffers: the loads of the next step are in flight while the
+    // current one is computed.  Trip counts are block-uniform; the rest of
+    // the row follows as single steps, only the last one masked.
+    const int nfull = n / (U * OOS_BLOCK);
+    float xa[U][D], da[U][NL], xb[U][D], db[U][NL];
+    auto load = [&](float (&x)[U][D], float (&dv)[U][NL], int jb) {
+        const int j = jb + tid;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int o = 0; o < NL; ++o)
+                dv[u][o] = __uint_as_float(
+                    __builtin_amdgcn_raw_buffer_load_b32(rs[o], (j + u * OOS_BLOCK) * 4, 0, 0));
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < D; ++k)
+                x[u][k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+                    xr, (j + u * OOS_BLOCK) * 4, k * npad * 4, 0));
+    };
+    auto compute = [&](const float (&x)[U][D], const float (&dv)[U][NL]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) pair_step<D, NL, FID, false>(x[u], dv[u], yv, true, s);
+    };
+    if (nfull > 0) load(xa, da, 0);
+    int st = 0;
+    for (; st + 2 <= nfull; st += 2) {
+        load(xb, db, (st + 1) * U * OOS_BLOCK);
+        compute(xa, da);
+        if (st + 2 < nfull) load(xa, da, (st + 2) * U * OOS_BLOCK);
+        compute(xb, db);
+    }
+    if (st < nfull) compute(xa, da);
+    for (int jb = nfull * U * OOS_BLOCK; jb < n; jb += OOS_BLOCK) {
+        // past n: delta reads 0 (buffer range), the X index is clamped and
+        // the fidelity term is masked
+        const int j = jb + tid;
+        const bool inside = j < n;
+        const int jc = inside ? j : n - 1;
+        float x[D], dv[NL];
+#pragma unroll
+        for (int o = 0; o < NL; ++o)
+            dv[o] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs[o], j * 4, 0, 0));
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+            x[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(xr, jc * 4, k * npad * 4, 0));
+        if (jb + OOS_BLOCK <= n) pair_step<D, NL, FID, false>(x, dv, yv, true, s);
+        else pair_step<D, NL, FID, true>(x, dv, yv, inside, s);
+    }
+    float p[VL];
+#pragma unroll
+    for (int q = 0; q < VL; ++q) p[q] = q < NL * NV ? s[q / NV][q % NV] : 0.f;
+    float c[VL / 8];
+    reduce_scatter8<VL>(p, c, lane);
+    if ((lane & 7) == 0) {
+        const int base = ((lane >> 3) & 1) * (VL / 8) + ((lane >> 4) & 1) * (VL / 4) +
+                         ((lane >> 5) & 1) * (VL / 2);
+#pragma unroll
+        for (int r = 0; r < VL / 8; ++r) dst[base + r] = c[r];
+    }
+}
+
+template <int D, int NL, int U>
+__device__ __forceinline__ void stream_pass(const OOSArgs &a, bool fid, int o0,
+                                            const int (&ord)[4], const float *ys, float *red,
+                                            int VP, int tid) {
+    const int wv = tid / WAVE;
+    for (int i = 0; i < a.m; ++i) {
+        float *dst = red + ((size_t)wv * a.m + i) * VP;
+        if (fid) stream_modality<D, NL, U, true>(a, i, o0, ord, ys, dst, tid);
+        else stream_modality<D, NL, U, false>(a, i, o0, ord, ys, dst, tid);
+    }
+}
+
+constexpr int OB = OOS_WAVES;  // objects per workgroup: one per wave for the update
+
+template <int D, int U>
+__global__ __launch_bounds__(OOS_BLOCK) void oos_kernel(OOSArgs a,
+                                                        const double *__restrict__ colsum) {
+    constexpr int NV = D + 1;                       // S (D components), fidelity
+    constexpr int VP = (OB * NV + 7) / 8 * 8;       // values reduced per wave
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int m = a.m;
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
+    const int mD = m * D;
     const int o0 = blockIdx.x * OB;
 
-    for (int q = tid; q < OB * m * D; q += OOS_BLOCK) {
-        const int o = q / (m * D), r = q - o * m * D, i = r / D, k = r - i * D;
-        ys[o][i][k] = (o0 + o < a.k) ? a.Y[((size_t)(o0 + o) * m + i) * D + k] : 0.f;
-    }
+    // LDS: red [waves][m][VP] floats | T [waves][m][D] doubles |
+    // prev [OB] doubles | status [OB] ints | y [OB][m][D] floats.
+    // Physical slot p holds object o0 + p for the whole kernel.
+    unsigned char *q = lds_raw;
+    float *red = reinterpret_cast<float *>(q);
+    q += (size_t)OOS_WAVES * m * VP * 4;
+    double *T = reinterpret_cast<double *>(q) + (size_t)wv * mD;
+    q += (size_t)OOS_WAVES * mD * 8;
+    double *prev = reinterpret_cast<double *>(q);
+    q += OB * 8;
+    int *status = reinterpret_cast<int *>(q);
+    q += OB * 4;
+    float *ys = reinterpret_cast<float *>(q);
+
+    // Live slots, compacted: ord[c] is the physical slot of live position c
+    // (identical in every thread).
+    int ord[OB];
+#pragma unroll
+    for (int c = 0; c < OB; ++c) ord[c] = c;
+    int nl = min(OB, a.k - o0);
+    for (int e = tid; e < nl * mD; e += OOS_BLOCK) ys[e] = a.Y[(size_t)o0 * mD + e];
     if (tid < OB) {
-        live[tid] = (o0 + tid < a.k) ? 1 : 0;
         prev[tid] = 0.0;
+        status[tid] = 0;
     }
     __syncthreads();
 
+    const bool fid_always = a.target != nullptr || a.tol > 0.0;
     for (int t = 0;; ++t) {
         // ---- stream pass at y_t ------------------------------------------
-        for (int i = 0; i < m; ++i) {
-            float s[OB][NV];
-#pragma unroll
-            for (int o = 0; o < OB; ++o)
-#pragma unroll
-                for (int v = 0; v < NV; ++v) s[o][v] = 0.f;
-            float yv[OB][D];
-            bool lv[OB];
-#pragma unroll
-            for (int o = 0; o < OB; ++o) {
-                lv[o] = live[o] != 0;
-#pragma unroll
-                for (int k = 0; k < D; ++k) yv[o][k] = ys[o][i][k];
-            }
-            const float *Xi = a.Xs + (size_t)i * D * npad;
-            for (int j = tid; j < n; j += OOS_BLOCK) {
-                float x[D];
-#pragma unroll
-                for (int k = 0; k < D; ++k) x[k] = Xi[(size_t)k * npad + j];
-                float dl[OB];
-#pragma unroll
-                for (int o = 0; o < OB; ++o)
-                    dl[o] = lv[o] ? a.dnew[((size_t)(o0 + o) * m + i) * n + j] : 0.f;
-#pragma unroll
-                for (int o = 0; o < OB; ++o) {
-                    if (!lv[o]) continue;
-                    float d2 = 0.f;
-#pragma unroll
-                    for (int k = 0; k < D; ++k) {
-                        const float df = x[k] - yv[o][k];
-                        d2 = fmaf(df, df, d2);
-                    }
-                    const float rs = __builtin_amdgcn_rsqf(fmaxf(d2, FLT_MIN));
-                    // eq:B's d = 0 rule for the new point
-                    const float r = (d2 > 0.f) ? dl[o] * rs : 0.f;
-                    s[o][0] += r;
-#pragma unroll
-                    for (int k = 0; k < D; ++k) s[o][1 + k] = fmaf(r, x[k], s[o][1 + k]);
-                    const float e = dl[o] - d2 * rs;
-                    s[o][NV - 1] = fmaf(e, e, s[o][NV - 1]);
-                }
-            }
-#pragma unroll
-            for (int o = 0; o < OB; ++o)
-#pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    const float w = wave_sum_f(s[o][v]);
-                    if (lane == 0) red[wv][o][v] = w;
-                }
-            __syncthreads();
-            for (int q = tid; q < OB * NV; q += OOS_BLOCK) {
-                const int o = q / NV, v = q - o * NV;
-                double tot = 0.0;
-                for (int w = 0; w < OOS_WAVES; ++w) tot += (double)red[w][o][v];
-                acc[o][i][v] = tot;
-            }
-            __syncthreads();
-        }
-        // ---- per object: stress, stop rules, transform ------------------
-        if (tid < OB) {
-            const int o = tid;
-            if (live[o]) {
-                double sig = 0.0;
-                for (int i = 0; i < m; ++i) sig += a.wmat[i * m + i] * acc[o][i][NV - 1];
-                for (int i = 0; i < m; ++i)
-                    for (int l = i + 1; l < m; ++l) {
-                        double dd = 0.0;
-                        for (int k = 0; k < D; ++k) {
-                            const double df = (double)ys[o][i][k] - (double)ys[o][l][k];
-                            dd += df * df;
-                        }
-                        sig += a.wmat[i * m + l] * dd;
-                    }
-                bool stop = false;
-                if (a.target && sig <= a.target[o0 + o]) stop = true;
-                else if (a.tol > 0.0 && t > 0 && prev[o] - sig < a.tol * prev[o]) stop = true;
-                else if (t == a.iters) stop = true;
-                if (stop) {
-                    live[o] = 0;
-                    if (a.stress_out) a.stress_out[o0 + o] = sig;
-                    if (a.iters_out) a.iters_out[o0 + o] = t;
-                }
-                prev[o] = sig;
-            }
+        const bool fid = fid_always || t == a.iters;
+        switch (nl) {
+        case 4: stream_pass<D, 4, U>(a, fid, o0, ord, ys, red, VP, tid); break;
+        case 3: stream_pass<D, 3, U>(a, fid, o0, ord, ys, red, VP, tid); break;
+        case 2: stream_pass<D, 2, U>(a, fid, o0, ord, ys, red, VP, tid); break;
+        default: stream_pass<D, 1, U>(a, fid, o0, ord, ys, red, VP, tid); break;
         }
         __syncthreads();
-        // y <- L22^-1 (xi + diag(psi) y), FP64 arithmetic; staged so that
-        // every thread reads the old y before any is overwritten.
-        for (int q = tid; q < OB * m * D; q += OOS_BLOCK) {
-            const int o = q / (m * D), r = q - o * m * D, i = r / D, k = r - i * D;
-            if (!live[o]) continue;
-            double v = 0.0;
+        // ---- live position wv, in its wave: stress, stop rules, transform --
+        if (wv < nl) {
+            const int c = wv;
+            int p = ord[0];
+#pragma unroll
+            for (int e = 1; e < OB; ++e)
+                if (c == e) p = ord[e];
+            float *yo = ys + p * mD;
+            double sig = 0.0;
             for (int l = 0; l < m; ++l) {
                 const double wl = a.wmat[l * m + l];
-                const double xi = wl * (colsum[l * D + k] - acc[o][l][1 + k]);
-                const double psi = wl * acc[o][l][0];
-                v += a.Linv[i * m + l] * (xi + psi * (double)ys[o][l][k]);
+                double f = 0.0;
+                for (int w = 0; w < OOS_WAVES; ++w)
+                    f += (double)red[((size_t)w * m + l) * VP + c * NV + D];
+                sig += wl * f;
+                for (int k = 0; k < D; ++k) {
+                    double S = 0.0;
+                    for (int w = 0; w < OOS_WAVES; ++w)
+                        S += (double)red[((size_t)w * m + l) * VP + c * NV + k];
+                    T[l * D + k] = wl * (colsum[l * D + k] - S);
+                }
             }
-            ynew[o][i][k] = (float)v;
+            for (int i = 0; i < m; ++i)
+                for (int l = i + 1; l < m; ++l) {
+                    double dd = 0.0;
+                    for (int k = 0; k < D; ++k) {
+                        const double df = (double)yo[i * D + k] - (double)yo[l * D + k];
+                        dd += df * df;
+                    }
+                    sig += a.wmat[i * m + l] * dd;
+                }
+            const int o = o0 + p;
+            bool stop = false;
+            if (a.target && sig <= a.target[o]) stop = true;
+            else if (a.tol > 0.0 && t > 0 && prev[p] - sig < a.tol * prev[p]) stop = true;
+            else if (t == a.iters) stop = true;
+            if (__builtin_amdgcn_readfirstlane((int)stop)) {
+                for (int e = lane; e < mD; e += WAVE) a.Y[(size_t)o * mD + e] = yo[e];
+                if (lane == 0) {
+                    if (a.stress_out) a.stress_out[o] = sig;
+                    if (a.iters_out) a.iters_out[o] = t;
+                    status[p] = 1;
+                }
+            } else {
+                // y_{t+1} = L22^-1 T (T depends only on this pass's sums);
+                // lane e writes component e.
+                for (int e = lane; e < mD; e += WAVE) {
+                    const int i = e / D, k = e - i * D;
+                    double v = 0.0;
+                    for (int l = 0; l < m; ++l) v += a.Linv[i * m + l] * T[l * D + k];
+                    yo[e] = (float)v;
+                }
+                if (lane == 0) prev[p] = sig;
+            }
         }
         __syncthreads();
-        for (int q = tid; q < OB * m * D; q += OOS_BLOCK) {
-            const int o = q / (m * D), r = q - o * m * D, i = r / D, k = r - i * D;
-            if (live[o]) ys[o][i][k] = ynew[o][i][k];
+        // ---- drop finished slots, keeping the order of the rest ----------
+        int w = 0;
+        int nord[OB];
+#pragma unroll
+        for (int c = 0; c < OB; ++c) nord[c] = ord[c];
+#pragma unroll
+        for (int c = 0; c < OB; ++c) {
+            if (c < nl && !status[ord[c]]) {
+#pragma unroll
+                for (int e = 0; e < OB; ++e)
+                    if (e == w) nord[e] = ord[c];
+                ++w;
+            }
         }
-        if (tid == 0) {
-            int anyl = 0;
-            for (int o = 0; o < OB; ++o) anyl |= live[o];
-            any_live = anyl;
-        }
-        __syncthreads();
-        if (!any_live) break;
-    }
-    for (int q = tid; q < OB * m * D; q += OOS_BLOCK) {
-        const int o = q / (m * D), r = q - o * m * D, i = r / D, k = r - i * D;
-        if (o0 + o < a.k) a.Y[((size_t)(o0 + o) * m + i) * D + k] = ys[o][i][k];
+#pragma unroll
+        for (int c = 0; c < OB; ++c) ord[c] = __builtin_amdgcn_readfirstlane(nord[c]);
+        nl = __builtin_amdgcn_readfirstlane(w);
+        if (nl == 0) break;
     }
 }
 
@@ -200,9 +370,12 @@ __global__ void colsum_kernel(const float *__restrict__ Xs, int m, int n,
 
 template <int D>
 hipError_t launch_oos_d(const OOSArgs &a, const double *colsum, hipStream_t s) {
-    constexpr int OB = 8;
+    constexpr int U = 2;
+    constexpr int NV = D + 1, VP = (OB * NV + 7) / 8 * 8;
+    const size_t lds = (size_t)OOS_WAVES * a.m * VP * 4 + (size_t)OOS_WAVES * a.m * D * 8 +
+                       OB * 8 + OB * 4 + (size_t)OB * a.m * D * 4;
     const unsigned nb = (unsigned)((a.k + OB - 1) / OB);
-    oos_kernel<D, OB><<<nb, OOS_BLOCK, 0, s>>>(a, colsum);
+    oos_kernel<D, U><<<nb, OOS_BLOCK, lds, s>>>(a, colsum);
     return hipGetLastError();
 }
 

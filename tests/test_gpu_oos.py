@@ -58,7 +58,8 @@ def _run(ctx, X, wmat, dnew, Y0, iters, **kw):
 
 
 @pytest.mark.parametrize("m,n,d,k", [(2, 200, 2, 9), (3, 257, 3, 17), (2, 1000, 5, 40),
-                                     (1, 100, 2, 8), (4, 64, 8, 5), (2, 3, 1, 3)])
+                                     (1, 100, 2, 8), (4, 64, 8, 5), (2, 3, 1, 3), (8, 300, 3, 6),
+                                     (2, 1536, 4, 13)])
 def test_oos_parity(ctx, m, n, d, k):
     X, wmat, dnew, Y0 = _oos_problem(30 + n, m, n, d, k)
     for iters in (0, 1, 25):
