@@ -153,6 +153,16 @@ int fjofc_oos(fjofc_ctx *ctx, const float *X_in, int m, int n, int d,
               int *iters_out, int sync, void *stream);
 
 /*
+ * Nearest-in-sample start for fjofc_oos (a comparison start; the paper
+ * starts from a random point): Y[o][i] = row i*n + j* of X_in, j* being the
+ * smallest index minimising delta_new[o][i][j] over j.  Arrays as for
+ * fjofc_oos; does not synchronise the stream.
+ */
+int fjofc_oos_nearest_start(fjofc_ctx *ctx, const float *X_in, int m, int n,
+                            int d, const float *delta_new, int k, float *Y,
+                            void *stream);
+
+/*
  * Batched in-sample fJOFC: many independent problems of different m, n, d
  * advanced in lockstep (one stream launch per kernel variant and one
  * combine launch per transform), the whole loop captured once into a HIP
@@ -215,10 +225,12 @@ int fjofc_mlp_get_params(fjofc_mlp *net, float *const *W, float *const *b,
 /* out (B x dims[L] FP32) = network(x), x: B x dims[0] BF16 (uint16 bits). */
 int fjofc_mlp_forward(fjofc_mlp *net, const unsigned short *x, int B,
                       float *out, void *stream);
-/* Warm start for fjofc_oos: Y (B x m x dims[L] FP32) receives the
- * network's point for every one of the object's m modalities.            */
+/* Warm start for fjofc_oos: Y is B x m x d FP32.  A network with
+ * dims[L] == d gives one point that all m modalities start from; dims[L] ==
+ * m*d gives one point per modality (row-major m x d).  Any other width is
+ * FJOFC_EINVAL.                                                           */
 int fjofc_mlp_predict_start(fjofc_mlp *net, const unsigned short *x, int B,
-                            int m, float *Y, void *stream);
+                            int m, int d, float *Y, void *stream);
 /* Forward, MSE against y (B x dims[L] FP32), backward: the gradients are
  * kept in the network (fjofc_mlp_get_grads); loss (optional, FP64).      */
 int fjofc_mlp_backward(fjofc_mlp *net, const unsigned short *x, const float *y,

@@ -136,3 +136,18 @@ def oos_stress(X, wmat, dnew, y):
         for b in range(a):
             s += Wo[a, b] * (Do[a, b] - dist[a, b]) ** 2
     return float(s)
+
+
+def nearest_start(X: np.ndarray, dnew: np.ndarray) -> np.ndarray:
+    """Comparison start for the out-of-sample problem (not the paper's, which
+    starts at random): for every new object o and modality i, the in-sample
+    point X^(i)_j whose dissimilarity to o is smallest (numpy's argmin takes
+    the first of tied minima).  X: (m n) x d, dnew: k x m x n -> k x m x d."""
+    k, m, n = dnew.shape
+    d = X.shape[1]
+    Y = np.empty((k, m, d), dtype=X.dtype)
+    for o in range(k):
+        for i in range(m):
+            j = int(np.argmin(dnew[o, i]))
+            Y[o, i] = X[i * n + j]
+    return Y

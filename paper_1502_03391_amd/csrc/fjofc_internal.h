@@ -129,6 +129,9 @@ struct OOSArgs {
 };
 // colsum: workspace of m * D doubles (sum_j X^(i)_j, computed first).
 hipError_t launch_oos(const OOSArgs &a, double *colsum, hipStream_t s);
+// Y[o][i] = X row i*n + argmin_j delta_new[o][i][j] (X in the ABI layout).
+hipError_t launch_nearest(const float *X, int m, int n, int d, const float *dnew, int k,
+                          float *Y, hipStream_t s);
 
 // ---- warm-start network (mlp.hip) -------------------------------------
 enum { GEMM_HIDDEN = 0, GEMM_LAST = 1, GEMM_BWD = 2, GEMM_STORE = 3 };
@@ -148,7 +151,10 @@ hipError_t launch_adam(float *p, const float *g, float *m, float *v, uint16_t *p
                        float lr, float b1, float b2, float eps, float c1, float c2,
                        hipStream_t s);
 hipError_t launch_to_bf16(const float *x, uint16_t *y, long n, hipStream_t s);
-hipError_t launch_broadcast(const float *out, int B, int m, int d, float *Y, hipStream_t s);
+// Y (B x m x d) from the network output (B x P): P == d repeats the point
+// for every modality, P == m d copies.
+hipError_t launch_broadcast(const float *out, int B, int m, int d, int P, float *Y,
+                            hipStream_t s);
 hipError_t launch_features(const float *dnew, int k, int m, int n, const int *lm, int L,
                            const float *mu, const float *isd, uint16_t *x, hipStream_t s);
 

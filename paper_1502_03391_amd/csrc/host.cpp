@@ -712,6 +712,19 @@ int fjofc_oos(fjofc_ctx *ctx, const float *X_in, int m, int n, int d,
     return FJOFC_OK;
 }
 
+int fjofc_oos_nearest_start(fjofc_ctx *ctx, const float *X_in, int m, int n, int d,
+                            const float *delta_new, int k, float *Y, void *stream) {
+    if (!ctx) return fail(FJOFC_EINVAL, "ctx is NULL");
+    if (m < 1 || m > FJOFC_MAX_M) return fail(FJOFC_EINVAL, "m=%d outside [1,%d]", m, FJOFC_MAX_M);
+    if (n < 1) return fail(FJOFC_EINVAL, "n=%d must be >= 1", n);
+    if (d < 1 || d > FJOFC_MAX_D) return fail(FJOFC_EINVAL, "d=%d outside [1,%d]", d, FJOFC_MAX_D);
+    if (k < 0) return fail(FJOFC_EINVAL, "k=%d must be >= 0", k);
+    if (k > 0 && (!X_in || !delta_new || !Y)) return fail(FJOFC_EINVAL, "NULL array");
+    DeviceGuard dg(ctx->device);
+    HIP_TRY(launch_nearest(X_in, m, n, d, delta_new, k, Y, static_cast<hipStream_t>(stream)));
+    return FJOFC_OK;
+}
+
 int fjofc_profile_enable(fjofc_ctx *ctx, int on) {
     if (!ctx) return fail(FJOFC_EINVAL, "ctx is NULL");
     DeviceGuard dg(ctx->device);

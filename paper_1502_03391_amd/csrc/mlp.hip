@@ -197,23 +197,24 @@ __global__ void features_kernel(const float *__restrict__ dnew, int k, int m, in
 
 // Start configuration of the out-of-sample iteration from the network's
 // consensus point: Y[o][i][c] = out[o][c] for every modality i.
-__global__ void broadcast_kernel(const float *__restrict__ out, int B, int m, int d,
+__global__ void broadcast_kernel(const float *__restrict__ out, int B, int m, int d, int P,
                                  float *__restrict__ Y) {
     const long tot = (long)B * m * d;
     for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < tot;
          q += (long)gridDim.x * blockDim.x) {
         const long o = q / ((long)m * d);
-        const int c = (int)(q % d);
-        Y[q] = out[o * d + c];
+        const int c = P == d ? (int)(q % d) : (int)(q - o * m * d);
+        Y[q] = out[o * P + c];
     }
 }
 
 }  // namespace
 
-hipError_t launch_broadcast(const float *out, int B, int m, int d, float *Y, hipStream_t s) {
+hipError_t launch_broadcast(const float *out, int B, int m, int d, int P, float *Y,
+                            hipStream_t s) {
     const long tot = (long)B * m * d;
     const unsigned nb = (unsigned)std::min<long>(4096, (tot + 255) / 256);
-    broadcast_kernel<<<nb > 0 ? nb : 1, 256, 0, s>>>(out, B, m, d, Y);
+    broadcast_kernel<<<nb > 0 ? nb : 1, 256, 0, s>>>(out, B, m, d, P, Y);
     return hipGetLastError();
 }
 

@@ -198,16 +198,20 @@ int fjofc_mlp_forward(fjofc_mlp *n, const unsigned short *x, int B, float *out, 
     return FJOFC_OK;
 }
 
-int fjofc_mlp_predict_start(fjofc_mlp *n, const unsigned short *x, int B, int m, float *Y,
-                            void *stream) {
+int fjofc_mlp_predict_start(fjofc_mlp *n, const unsigned short *x, int B, int m, int d,
+                            float *Y, void *stream) {
     int rc = check_batch(n, B);
     if (rc) return rc;
-    if (!x || !Y || m < 1) return set_error(FJOFC_EINVAL, "bad argument");
+    if (!x || !Y || m < 1 || d < 1) return set_error(FJOFC_EINVAL, "bad argument");
+    const int P = n->dims[n->L];
+    if (P != d && P != m * d)
+        return set_error(FJOFC_EINVAL, "network output width %d is neither d=%d nor m*d=%d", P,
+                         d, m * d);
     Dev dg(n->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     rc = forward(n, x, B, s);
     if (rc) return rc;
-    HIP_CHECK(launch_broadcast(n->out, B, m, n->dims[n->L], Y, s));
+    HIP_CHECK(launch_broadcast(n->out, B, m, d, P, Y, s));
     return FJOFC_OK;
 }
 

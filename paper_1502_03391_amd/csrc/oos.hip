@@ -379,7 +379,49 @@ hipError_t launch_oos_d(const OOSArgs &a, const double *colsum, hipStream_t s) {
     return hipGetLastError();
 }
 
+// One wave per (object, modality) row: the smallest index of the row's
+// minimum (ties to the smaller index), then the in-sample point copied.
+__global__ __launch_bounds__(OOS_BLOCK) void nearest_kernel(const float *__restrict__ X, int m,
+                                                            int n, int d,
+                                                            const float *__restrict__ dnew,
+                                                            long rows, float *__restrict__ Y) {
+    const long row = (long)blockIdx.x * OOS_WAVES + threadIdx.x / WAVE;
+    if (row >= rows) return;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int i = (int)(row % m);
+    const float *dr = dnew + row * n;
+    float best = INFINITY;
+    int bj = n;
+    for (int j = lane; j < n; j += WAVE) {
+        const float v = dr[j];
+        if (v < best) {
+            best = v;
+            bj = j;
+        }
+    }
+#pragma unroll
+    for (int sh = 32; sh >= 1; sh >>= 1) {
+        const float ob = __shfl_xor(best, sh);
+        const int oj = __shfl_xor(bj, sh);
+        if (ob < best || (ob == best && oj < bj)) {
+            best = ob;
+            bj = oj;
+        }
+    }
+    if (bj >= n) bj = 0;  // a row of NaNs: no minimum, take object 0
+    if (lane < d) Y[row * d + lane] = X[((long)i * n + bj) * d + lane];
+}
+
 }  // namespace
+
+hipError_t launch_nearest(const float *X, int m, int n, int d, const float *dnew, int k,
+                          float *Y, hipStream_t s) {
+    const long rows = (long)k * m;
+    if (rows == 0) return hipSuccess;
+    nearest_kernel<<<(unsigned)((rows + OOS_WAVES - 1) / OOS_WAVES), OOS_BLOCK, 0, s>>>(
+        X, m, n, d, dnew, rows, Y);
+    return hipGetLastError();
+}
 
 hipError_t launch_oos(const OOSArgs &a, double *colsum, hipStream_t s) {
     colsum_kernel<<<(unsigned)(a.m * a.D), OOS_BLOCK, 0, s>>>(a.Xs, a.m, a.n, a.npad, a.D, colsum);

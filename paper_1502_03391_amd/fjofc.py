@@ -28,7 +28,7 @@ EXPORTS = ["fjofc_create", "fjofc_destroy", "fjofc_last_error", "fjofc_strerror"
            "fjofc_mlp_create", "fjofc_mlp_destroy", "fjofc_mlp_set_params",
            "fjofc_mlp_get_params", "fjofc_mlp_forward", "fjofc_mlp_backward",
            "fjofc_mlp_get_grads", "fjofc_mlp_adam", "fjofc_mlp_features",
-           "fjofc_mlp_predict_start"]
+           "fjofc_mlp_predict_start", "fjofc_oos_nearest_start"]
 
 
 class FjofcResult(C.Structure):
@@ -110,7 +110,8 @@ def lib():
         L.fjofc_mlp_get_params.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), vp]
         L.fjofc_mlp_forward.argtypes = [vp, vp, ip, vp, vp]
         L.fjofc_mlp_backward.argtypes = [vp, vp, vp, ip, vp, vp]
-        L.fjofc_mlp_predict_start.argtypes = [vp, vp, ip, ip, vp, vp]
+        L.fjofc_mlp_predict_start.argtypes = [vp, vp, ip, ip, ip, vp, vp]
+        L.fjofc_oos_nearest_start.argtypes = [vp, vp, ip, ip, ip, vp, ip, vp, vp]
         L.fjofc_mlp_get_grads.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), vp]
         L.fjofc_mlp_adam.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float, vp]
         L.fjofc_mlp_features.argtypes = [vp, vp, ip, ip, ip, vp, ip, vp, vp, vp, vp]
@@ -222,6 +223,20 @@ def fjofc_oos(ctx: Context, X_in, wmat, delta_new, Y, iters: int,
                            wp, _dev_ptr(delta_new, torch.float32, "delta_new"), k,
                            _dev_ptr(Y, torch.float32, "Y"), int(iters), float(tol),
                            tp, sp, itp, 1 if sync else 0, _stream_ptr(stream)))
+
+
+def fjofc_oos_nearest_start(ctx: Context, X_in, delta_new, Y, stream=None):
+    """Y[o][i] = the in-sample point of modality i nearest (smallest
+    dissimilarity, smallest index on ties) to new object o."""
+    import torch
+    k, m, n = (int(s) for s in delta_new.shape)
+    d = int(X_in.shape[1])
+    if tuple(Y.shape) != (k, m, d):
+        raise ValueError(f"Y must be {k} x {m} x {d}")
+    _check(lib().fjofc_oos_nearest_start(ctx.handle, _dev_ptr(X_in, torch.float32, "X_in"), m, n,
+                                         d, _dev_ptr(delta_new, torch.float32, "delta_new"), k,
+                                         _dev_ptr(Y, torch.float32, "Y"), _stream_ptr(stream)))
+    return Y
 
 
 def fjofc_profile_enable(ctx: Context, on: bool = True):
@@ -341,11 +356,12 @@ class Mlp:
                                        _dev_ptr(out, torch.float32, "out"), _stream_ptr(stream)))
         return out
 
-    def predict_start(self, x, m, Y, stream=None):
-        """Y (B x m x dims[-1]) = the network's point for every modality."""
+    def predict_start(self, x, Y, stream=None):
+        """Y (B x m x d): the network's point for every modality (output
+        width d) or one point per modality (output width m d)."""
         import torch
         _check(lib().fjofc_mlp_predict_start(self._h, _dev_ptr(x, torch.bfloat16, "x"),
-                                             int(x.shape[0]), int(m),
+                                             int(x.shape[0]), int(Y.shape[1]), int(Y.shape[2]),
                                              _dev_ptr(Y, torch.float32, "Y"), _stream_ptr(stream)))
         return Y
 

@@ -117,3 +117,22 @@ def test_features_kernel(ctx):
                              torch.from_numpy(mu).cuda(), torch.from_numpy(isd).cuda(), x)
     ref = ((dn[:, :, lm].reshape(k, m * L) - mu) * isd)
     np.testing.assert_array_equal(x.float().cpu().numpy(), omlp.bf16_round(ref.astype(np.float32)))
+
+
+@pytest.mark.parametrize("per_modality", [False, True])
+def test_predict_start_layouts(ctx, per_modality):
+    m, d, B = 3, 4, 50
+    dims = [24, 32, (m * d) if per_modality else d]
+    net, params, x, y, xb = _net(ctx, dims, B, 11)
+    out = net.forward(xb).cpu().numpy()
+    Y = torch.full((B, m, d), float("nan"), device="cuda")
+    net.predict_start(xb, Y)
+    Yc = Y.cpu().numpy()
+    want = out.reshape(B, m, d) if per_modality else np.repeat(out[:, None, :], m, axis=1)
+    np.testing.assert_array_equal(Yc, want)
+
+
+def test_predict_start_rejects_other_widths(ctx):
+    net, _, _, _, xb = _net(ctx, [24, 32, 7], 10, 5)
+    with pytest.raises(fjofc.FjofcError):
+        net.predict_start(xb, torch.empty((10, 2, 5), device="cuda"))

@@ -17,6 +17,7 @@ if gpu_available():
     import torch
     from paper_1502_03391_amd import fjofc
     from oracle import structured as orc
+    from oracle import dense as odense
 
 
 @pytest.fixture(scope="module")
@@ -103,3 +104,14 @@ def test_oos_leave_one_out_fixed_point(ctx):
     y = np.stack([Xs[i * n + j] for i in range(m)])[None].astype(np.float32)
     Yg, _, _ = _run(ctx, Xin, wmat, dnew, y, 20)
     assert np.abs(Yg - y).max() < 1e-4 * np.abs(Xs).max()
+
+
+@pytest.mark.parametrize("m,n,d,k", [(2, 1000, 5, 37), (3, 70, 2, 5), (1, 1, 1, 2)])
+def test_nearest_start(ctx, m, n, d, k):
+    rng = np.random.default_rng(n + k)
+    X = rng.standard_normal((m * n, d)).astype(np.float32)
+    # small integers, so that many rows have tied minima (smallest index wins)
+    dnew = rng.integers(0, 6, (k, m, n)).astype(np.float32)
+    Y = torch.empty((k, m, d), device="cuda")
+    fjofc.fjofc_oos_nearest_start(ctx, _dev(X), _dev(dnew), Y)
+    np.testing.assert_array_equal(Y.cpu().numpy(), odense.nearest_start(X, dnew))

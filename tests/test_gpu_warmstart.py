@@ -1,7 +1,10 @@
-"""GPU test of the learned warm start at a reduced size: the network is
-trained by the library's own kernels on out-of-sample solutions the method
-produced, and its starts must reach the plain start's final stress (within
-1e-4 relative) in fewer transforms than the plain start needed."""
+"""GPU test of the learned warm start at a reduced size (in-sample n=1500,
+64 landmarks, a 2x128 network, 20000 training objects): the network is
+trained by the library's own kernels on converged out-of-sample solutions
+the method produced, and its starts must reach the plain start's final
+stress (within 1e-4 relative) for nearly every held-out object, in far
+fewer transforms than the plain start used and fewer than the
+nearest-in-sample start needs."""
 import dataclasses
 
 import pytest
@@ -11,7 +14,7 @@ from tests.conftest import gpu_available
 pytestmark = pytest.mark.gpu
 
 
-def test_warm_start_beats_plain_start():
+def test_warm_start_beats_plain_and_nearest_starts():
     if not gpu_available():
         pytest.skip("no GPU")
     from paper_1502_03391_amd import fjofc, warmstart
@@ -25,6 +28,7 @@ def test_warm_start_beats_plain_start():
     finally:
         ctx.close()
     ev = r["eval"]
-    assert ev["warm"]["reached_frac"] >= 0.75
-    assert ev["warm"]["iters_mean"] < 0.8 * ev["oos_iters_cap"]
-    assert ev["warm"]["iters_p50"] < ev["oos_iters_cap"]
+    assert ev["warm"]["reached_frac"] >= 0.95
+    assert ev["warm"]["iters_mean"] < 0.5 * ev["oos_iters_cap"]
+    assert ev["warm"]["iters_mean"] < ev["nearest"]["iters_mean"]
+    assert ev["warm"]["iters_p50"] < 0.4 * ev["oos_iters_cap"]

@@ -403,3 +403,20 @@ def test_oos_stress_monotone_and_stop_rules():
         if itt[o] > 0:
             Yp, sp, _ = orc.oos(X, wmat, dn[o:o + 1], Y0[o:o + 1], int(itt[o]) - 1)
             assert sp[0] > target[o]
+
+
+def test_nearest_start_brute_force():
+    # pinned by a brute-force scan written out independently: first index of
+    # the smallest value per (object, modality) row
+    rng = np.random.default_rng(5)
+    k, m, n, d = 4, 2, 9, 3
+    X = rng.standard_normal((m * n, d))
+    dnew = rng.integers(0, 3, (k, m, n)).astype(float)
+    Y = dense.nearest_start(X, dnew)
+    for o in range(k):
+        for i in range(m):
+            best, bj = None, None
+            for j in range(n):
+                if best is None or dnew[o, i, j] < best:
+                    best, bj = dnew[o, i, j], j
+            assert np.array_equal(Y[o, i], X[i * n + bj])
