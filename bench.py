@@ -27,22 +27,24 @@ METRIC = "fJOFC Δ-pairs/s & HBM GB/s; time-to-stress-tol, learned warm start vs
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_insample_stream_m3_n20000_d5.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1502_03391_amd", "csrc", "insample.hip")
+OOS_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_oos_m2_n10000_d5.json")
+OOS_SRC = os.path.join(ROOT, "paper_1502_03391_amd", "csrc", "oos.hip")
 
 
-def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
+def kernel_hash(src=KERNEL_SRC) -> str:
+    with open(src, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def load_traffic():
-    """HBM bytes per interior-stream launch from committed rocprofv3 counter
+def load_traffic(path=TRAFFIC_FILE, src=KERNEL_SRC):
+    """HBM bytes per launch of a kernel from committed rocprofv3 counter
     runs, or None when absent or taken on a different kernel source."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_sha") != kernel_hash():
+    if t.get("kernel_sha") != kernel_hash(src):
         return None
     return t.get("bytes_per_launch")
 
@@ -60,7 +62,7 @@ def parse():
     ap.add_argument("--iters", type=int, default=None,
                     help="transforms per step (default: the workload's 300); "
                          "for short profiled runs only")
-    ap.add_argument("--extras", default="oos,batched",
+    ap.add_argument("--extras", default="oos,batched,warmstart",
                     help="comma list of extra workloads to measure after the main one "
                          "(oos, batched, warmstart) or 'none'")
     return ap.parse_args()
@@ -166,6 +168,8 @@ def main():
         out["extra"]["oos"] = bench_oos(ctx)
     if "batched" in extras:
         out["extra"]["batched"] = bench_batched(ctx)
+    if "warmstart" in extras:
+        out["extra"]["warmstart"] = bench_warmstart(ctx)
     ctx.close()
     print(json.dumps(out), flush=True)
 
@@ -220,10 +224,28 @@ def bench_oos(ctx):
          "seconds": sec, "triples_per_s": triples / sec, "objects_per_s": sp.k / sec,
          "roofline": {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                       "frac": gbs / PEAK_HBM_GBS, "kernel": "oos_kernel",
+                      "traffic": load_traffic(OOS_TRAFFIC_FILE, OOS_SRC),
+                      "traffic_per": "launch of 4096 objects, 101 passes",
                       "launches": prof["oos_launches"],
                       "avg_launch_ms": prof["oos_ms"] / max(1, prof["oos_launches"])},
          "mean_stress": float(stress.mean())}
     del dnew
+    torch.cuda.empty_cache()
+    return r
+
+
+def bench_warmstart(ctx):
+    """Learned warm start: in-sample m=2, n=10000, d=5; 200000 training
+    objects whose targets are converged out-of-sample solutions; network
+    512 -> 3 x 512 GELU -> 10 (BF16 matrix cores), 20 epochs; 50000
+    held-out objects refined until their stress is within 1e-4 relative of
+    the plain start's stress after 100 transforms."""
+    import torch
+    from paper_1502_03391_amd import warmstart
+    t0 = time.perf_counter()
+    r = warmstart.run(ctx, warmstart.WarmStartConfig(), eval_objects=50000,
+                      log=lambda *a: print(*a, file=sys.stderr, flush=True))
+    r["total_seconds"] = time.perf_counter() - t0
     torch.cuda.empty_cache()
     return r
 

@@ -145,13 +145,25 @@ __global__ __launch_bounds__(256) void mse_kernel(const float *__restrict__ out,
     if (threadIdx.x == 0 && loss) loss[0] = sh[0] / (double)tot;
 }
 
-// Bias gradient: column sums of G (B x N), FP64 accumulation in row order.
-__global__ void colsum_kernel(const float *__restrict__ G, int B, int N, float *__restrict__ db) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= N) return;
+// Bias gradient: column sums of G (B x N).  A workgroup owns 64 columns;
+// its 16 row groups (rows r = g, g + 16, ...) accumulate in FP64 and are
+// added in a fixed order, so the result does not depend on scheduling.
+constexpr int CS_COLS = 64, CS_GROUPS = 16;
+__global__ __launch_bounds__(CS_COLS *CS_GROUPS) void colsum_kernel(
+    const float *__restrict__ G, int B, int N, float *__restrict__ db) {
+    __shared__ double part[CS_GROUPS][CS_COLS];
+    const int cl = threadIdx.x % CS_COLS, g = threadIdx.x / CS_COLS;
+    const int c = blockIdx.x * CS_COLS + cl;
     double s = 0.0;
-    for (int r = 0; r < B; ++r) s += (double)G[(long)r * N + c];
-    db[c] = (float)s;
+    if (c < N)
+        for (int r = g; r < B; r += CS_GROUPS) s += (double)G[(long)r * N + c];
+    part[g][cl] = s;
+    __syncthreads();
+    if (g == 0 && c < N) {
+        double t = 0.0;
+        for (int q = 0; q < CS_GROUPS; ++q) t += part[q][cl];
+        db[c] = (float)t;
+    }
 }
 
 // Adam with bias correction on the FP32 masters; refreshes the BF16 copy.
@@ -238,7 +250,8 @@ hipError_t launch_mse(const float *out, const float *y, int B, int k, float *G, 
 }
 
 hipError_t launch_colsum(const float *G, int B, int N, float *db, hipStream_t s) {
-    colsum_kernel<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(G, B, N, db);
+    if (N <= 0) return hipSuccess;
+    colsum_kernel<<<(unsigned)((N + CS_COLS - 1) / CS_COLS), CS_COLS * CS_GROUPS, 0, s>>>(G, B, N, db);
     return hipGetLastError();
 }
 
