@@ -137,15 +137,22 @@ hipError_t launch_nearest(const float *X, int m, int n, int d, const float *dnew
 enum { GEMM_HIDDEN = 0, GEMM_LAST = 1, GEMM_BWD = 2, GEMM_STORE = 3 };
 struct GemmEpi {
     const float *bias;  // HIDDEN, LAST
-    float *outf;        // Z (HIDDEN), output (LAST), g (BWD), C (STORE)
-    uint16_t *outb;     // BF16 GELU(Z) (HIDDEN), BF16 g (BWD)
-    const float *Z;     // pre-activations (BWD)
-    long ldc;
+    float *outf;        // Z (HIDDEN), output (LAST), g (BWD), C (STORE); row-major, ldc
+    uint16_t *outb;     // BF16 GELU(Z) (HIDDEN), BF16 g (BWD); row-major, ldc
+    uint16_t *outbT;    // the same BF16 values transposed (column-major, ldt); optional
+    const float *Z;     // pre-activations (BWD), row-major, ldc
+    long ldc, ldt;
 };
-hipError_t launch_gemm(int epi, int M, int N, int K, const uint16_t *A, long sam, long sak,
-                       const uint16_t *B, long sbk, long sbn, const GemmEpi &e, hipStream_t s);
+// C (M x N) = A (M x K) B (K x N) with both operands stored k-contiguous:
+// A(m, k) = A[m lda + k], B(k, n) = Bt[n ldb + k].  BF16 in, FP32 accumulate.
+hipError_t launch_gemm(int epi, int M, int N, int K, const uint16_t *A, long lda,
+                       const uint16_t *Bt, long ldb, const GemmEpi &e, hipStream_t s);
+// out (C x R, ld_out) = transpose of in (R x C, ld_in), BF16.
+hipError_t launch_transpose16(const uint16_t *in, long ld_in, int R, int C, uint16_t *out,
+                              long ld_out, hipStream_t s);
+// GbT (optional): the BF16 gradient transposed (k x B, leading dimension ldt).
 hipError_t launch_mse(const float *out, const float *y, int B, int k, float *G, uint16_t *Gb,
-                      double *loss, hipStream_t s);
+                      uint16_t *GbT, long ldt, double *loss, hipStream_t s);
 hipError_t launch_colsum(const float *G, int B, int N, float *db, hipStream_t s);
 hipError_t launch_adam(float *p, const float *g, float *m, float *v, uint16_t *p16, long n,
                        float lr, float b1, float b2, float eps, float c1, float c2,

@@ -15,7 +15,6 @@
 namespace fjofc {
 namespace {
 
-typedef short s4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 // FP32 -> BF16, round to nearest even (finite inputs).
@@ -34,96 +33,156 @@ __device__ __forceinline__ float gelu_grad(float z) {
            z * 0.39894228040143268f * expf(-0.5f * z * z);
 }
 
-// C (M x N) = A (M x K) B (K x N), A(m,k) = A[m sam + k sak],
-// B(k,n) = B[k sbk + n sbn].  64 x 64 tile per workgroup of four
-// wavefronts (2 x 2, 32 x 32 each as 2 x 2 MFMA 16x16x16 tiles), K in steps
-// of 32 staged through LDS (B stored transposed so both operands are read
-// as 4 consecutive BF16 per lane).  Operand layouts of the 16x16x16 BF16
-// MFMA: lane l holds A[l % 16][4 (l / 16) + j], B[4 (l / 16) + j][l % 16],
-// and receives C[4 (l / 16) + j][l % 16], j = 0..3.
-constexpr int GB = 64, GK = 32, GPAD = 4;
+// C (M x N) = A (M x K) B (K x N), both operands k-contiguous: A(m, k) =
+// A[m lda + k], B(k, n) = Bt[n ldb + k] (the library keeps transposed BF16
+// copies of weights, activations and gradients, so every product reads
+// both operands this way).  A workgroup of four wavefronts covers 64 x 64
+// outputs, each wavefront 32 x 32 as 2 x 2 tiles of the gfx950 BF16 matrix
+// instruction 16x16x32 (FP32 accumulation).  Operand layout of that
+// instruction: lane l supplies A[l % 16][8 (l / 16) + e] and
+// B[8 (l / 16) + e][l % 16], e = 0..7 (16 contiguous bytes of a k-row), and
+// receives C[4 (l / 16) + v][l % 16], v = 0..3.  Fragments are loaded
+// straight from global memory (L2-resident at these sizes), the next K step
+// while the current one is multiplied.
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+constexpr int GB = 64, GK = 32;
 
-template <int EPI>
+union Frag {
+    uint4 u;
+    bf8 v;
+    uint16_t h[8];
+};
+
+// Elements p[r ld + k .. k + 7], zero past R rows or K columns.  VEC: rows
+// are 16-byte aligned, so a whole in-range chunk is one 16-byte load.
+template <bool VEC>
+__device__ __forceinline__ bf8 load_frag(const uint16_t *__restrict__ p, long ld, int r, int R,
+                                         int k, int K) {
+    Frag f;
+    if (VEC && r < R && k + 8 <= K) {
+        f.u = *reinterpret_cast<const uint4 *>(p + (long)r * ld + k);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            f.h[e] = (r < R && k + e < K) ? p[(long)r * ld + k + e] : (uint16_t)0;
+    }
+    return f.v;
+}
+
+template <int EPI, bool VEC>
 __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K,
-                                                   const uint16_t *__restrict__ A, long sam,
-                                                   long sak, const uint16_t *__restrict__ B,
-                                                   long sbk, long sbn, GemmEpi e) {
-    __shared__ uint16_t As[GB][GK + GPAD];
-    __shared__ uint16_t Bs[GB][GK + GPAD];
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int wm = wv >> 1, wn = wv & 1;
-    const int m0 = blockIdx.y * GB, n0 = blockIdx.x * GB;
+                                                   const uint16_t *__restrict__ A, long lda,
+                                                   const uint16_t *__restrict__ Bt, long ldb,
+                                                   GemmEpi e) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int m0 = blockIdx.y * GB + (wv >> 1) * 32, n0 = blockIdx.x * GB + (wv & 1) * 32;
+    const int li = lane & 15, lk = (lane >> 4) * 8;
     f4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    bf8 a[2], b[2], an[2], bn[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        a[i] = load_frag<VEC>(A, lda, m0 + 16 * i + li, M, lk, K);
+        b[i] = load_frag<VEC>(Bt, ldb, n0 + 16 * i + li, N, lk, K);
+    }
     for (int k0 = 0; k0 < K; k0 += GK) {
+        const bool more = k0 + GK < K;
+        if (more) {
 #pragma unroll
-        for (int q = 0; q < (GB * GK) / 256; ++q) {
-            const int idx = tid + 256 * q;
-            // A tile, k fastest (coalesced when sak == 1)
-            const int ar = idx / GK, ac = idx % GK;
-            const int gm = m0 + ar, gk = k0 + ac;
-            As[ar][ac] = (gm < M && gk < K) ? A[(long)gm * sam + (long)gk * sak] : (uint16_t)0;
-            // B tile, n fastest (coalesced when sbn == 1), stored [n][k]
-            const int br = idx / GB, bc = idx % GB;
-            const int gk2 = k0 + br, gn = n0 + bc;
-            Bs[bc][br] = (gk2 < K && gn < N) ? B[(long)gk2 * sbk + (long)gn * sbn] : (uint16_t)0;
+            for (int i = 0; i < 2; ++i) {
+                an[i] = load_frag<VEC>(A, lda, m0 + 16 * i + li, M, k0 + GK + lk, K);
+                bn[i] = load_frag<VEC>(Bt, ldb, n0 + 16 * i + li, N, k0 + GK + lk, K);
+            }
         }
-        __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < GK / 16; ++kk) {
-            s4 a[2], b[2];
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-                a[i] = *reinterpret_cast<const s4 *>(&As[wm * 32 + i * 16 + (lane & 15)]
-                                                        [kk * 16 + 4 * (lane >> 4)]);
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int j = 0; j < 2; ++j)
-                b[j] = *reinterpret_cast<const s4 *>(&Bs[wn * 32 + j * 16 + (lane & 15)]
-                                                        [kk * 16 + 4 * (lane >> 4)]);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        if (more) {
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j],
-                                                                          0, 0, 0);
+            for (int i = 0; i < 2; ++i) {
+                a[i] = an[i];
+                b[i] = bn[i];
+            }
         }
-        __syncthreads();
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < 2; ++j) {
+            const int col = n0 + 16 * j + li;
+            const int rb = m0 + 16 * i + 4 * (lane >> 4);
+            if (col >= N) continue;
+            uint16_t hb[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
-                const int col = n0 + wn * 32 + j * 16 + (lane & 15);
-                if (row >= M || col >= N) continue;
+            for (int v = 0; v < 4; ++v) {
+                const int row = rb + v;
+                hb[v] = 0;
+                if (row >= M) continue;
                 const long o = (long)row * e.ldc + col;
-                const float v = acc[i][j][r];
+                const float x = acc[i][j][v];
                 if (EPI == GEMM_HIDDEN) {
-                    const float z = v + e.bias[col];
+                    const float z = x + e.bias[col];
                     e.outf[o] = z;
-                    e.outb[o] = f2bf(gelu(z));
+                    hb[v] = f2bf(gelu(z));
+                    e.outb[o] = hb[v];
                 } else if (EPI == GEMM_LAST) {
-                    e.outf[o] = v + e.bias[col];
+                    e.outf[o] = x + e.bias[col];
                 } else if (EPI == GEMM_BWD) {
-                    const float g = v * gelu_grad(e.Z[o]);
+                    const float g = x * gelu_grad(e.Z[o]);
                     e.outf[o] = g;
-                    e.outb[o] = f2bf(g);
+                    hb[v] = f2bf(g);
+                    e.outb[o] = hb[v];
                 } else {
-                    e.outf[o] = v;
+                    e.outf[o] = x;
                 }
             }
+            if ((EPI == GEMM_HIDDEN || EPI == GEMM_BWD) && e.outbT) {
+                uint16_t *t = e.outbT + (long)col * e.ldt + rb;
+                if (rb + 4 <= M && (e.ldt & 3) == 0) {
+                    uint2 w;
+                    w.x = (uint32_t)hb[0] | ((uint32_t)hb[1] << 16);
+                    w.y = (uint32_t)hb[2] | ((uint32_t)hb[3] << 16);
+                    *reinterpret_cast<uint2 *>(t) = w;
+                } else {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        if (rb + v < M) t[v] = hb[v];
+                }
+            }
+        }
 }
 
-// MSE over the batch and outputs: g = 2 (out - y) / (B k) (FP32 and BF16),
-// loss = mean (out - y)^2 (FP64, fixed-order reduction).
+// out (C x R) = transpose of in (R x C), BF16, through a 32 x 33 LDS tile.
+__global__ __launch_bounds__(256) void transpose16_kernel(const uint16_t *__restrict__ in,
+                                                          long ld_in, int R, int C,
+                                                          uint16_t *__restrict__ out,
+                                                          long ld_out) {
+    __shared__ uint16_t t[32][33];
+    const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int q = ty; q < 32; q += 8) {
+        const int r = r0 + q, c = c0 + tx;
+        t[q][tx] = (r < R && c < C) ? in[(long)r * ld_in + c] : (uint16_t)0;
+    }
+    __syncthreads();
+    for (int q = ty; q < 32; q += 8) {
+        const int c = c0 + q, r = r0 + tx;
+        if (c < C && r < R) out[(long)c * ld_out + r] = t[tx][q];
+    }
+}
+
+// MSE over the batch and outputs: g = 2 (out - y) / (B k) (FP32 and BF16,
+// and BF16 transposed when GbT is given), loss = mean (out - y)^2 (FP64,
+// fixed-order reduction).
 __global__ __launch_bounds__(256) void mse_kernel(const float *__restrict__ out,
                                                   const float *__restrict__ y, int B, int k,
                                                   float *__restrict__ G, uint16_t *__restrict__ Gb,
+                                                  uint16_t *__restrict__ GbT, long ldt,
                                                   double *__restrict__ loss) {
     __shared__ double sh[256];
     const long tot = (long)B * k;
@@ -134,7 +193,9 @@ __global__ __launch_bounds__(256) void mse_kernel(const float *__restrict__ out,
         s += (double)d * d;
         const float g = sc * d;
         G[q] = g;
-        Gb[q] = f2bf(g);
+        const uint16_t gb = f2bf(g);
+        Gb[q] = gb;
+        if (GbT) GbT[(q % k) * ldt + q / k] = gb;
     }
     sh[threadIdx.x] = s;
     __syncthreads();
@@ -230,22 +291,39 @@ hipError_t launch_broadcast(const float *out, int B, int m, int d, int P, float 
     return hipGetLastError();
 }
 
-hipError_t launch_gemm(int epi, int M, int N, int K, const uint16_t *A, long sam, long sak,
-                       const uint16_t *B, long sbk, long sbn, const GemmEpi &e, hipStream_t s) {
+template <int EPI>
+static hipError_t gemm_epi(bool vec, dim3 grid, int M, int N, int K, const uint16_t *A, long lda,
+                           const uint16_t *Bt, long ldb, const GemmEpi &e, hipStream_t s) {
+    if (vec) gemm_kernel<EPI, true><<<grid, 256, 0, s>>>(M, N, K, A, lda, Bt, ldb, e);
+    else gemm_kernel<EPI, false><<<grid, 256, 0, s>>>(M, N, K, A, lda, Bt, ldb, e);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm(int epi, int M, int N, int K, const uint16_t *A, long lda,
+                       const uint16_t *Bt, long ldb, const GemmEpi &e, hipStream_t s) {
     if (M <= 0 || N <= 0) return hipSuccess;
-    const dim3 grid((unsigned)((N + GB - 1) / GB), (unsigned)((M + GB - 1) / GB)), block(256);
+    const dim3 grid((unsigned)((N + GB - 1) / GB), (unsigned)((M + GB - 1) / GB));
+    const bool vec = (lda % 8 == 0) && (ldb % 8 == 0) &&
+                     ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(Bt)) & 15) == 0;
     switch (epi) {
-    case GEMM_HIDDEN: gemm_kernel<GEMM_HIDDEN><<<grid, block, 0, s>>>(M, N, K, A, sam, sak, B, sbk, sbn, e); break;
-    case GEMM_LAST: gemm_kernel<GEMM_LAST><<<grid, block, 0, s>>>(M, N, K, A, sam, sak, B, sbk, sbn, e); break;
-    case GEMM_BWD: gemm_kernel<GEMM_BWD><<<grid, block, 0, s>>>(M, N, K, A, sam, sak, B, sbk, sbn, e); break;
-    default: gemm_kernel<GEMM_STORE><<<grid, block, 0, s>>>(M, N, K, A, sam, sak, B, sbk, sbn, e); break;
+    case GEMM_HIDDEN: return gemm_epi<GEMM_HIDDEN>(vec, grid, M, N, K, A, lda, Bt, ldb, e, s);
+    case GEMM_LAST: return gemm_epi<GEMM_LAST>(vec, grid, M, N, K, A, lda, Bt, ldb, e, s);
+    case GEMM_BWD: return gemm_epi<GEMM_BWD>(vec, grid, M, N, K, A, lda, Bt, ldb, e, s);
+    default: return gemm_epi<GEMM_STORE>(vec, grid, M, N, K, A, lda, Bt, ldb, e, s);
     }
+}
+
+hipError_t launch_transpose16(const uint16_t *in, long ld_in, int R, int C, uint16_t *out,
+                              long ld_out, hipStream_t s) {
+    if (R <= 0 || C <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((C + 31) / 32), (unsigned)((R + 31) / 32));
+    transpose16_kernel<<<grid, 256, 0, s>>>(in, ld_in, R, C, out, ld_out);
     return hipGetLastError();
 }
 
 hipError_t launch_mse(const float *out, const float *y, int B, int k, float *G, uint16_t *Gb,
-                      double *loss, hipStream_t s) {
-    mse_kernel<<<1, 256, 0, s>>>(out, y, B, k, G, Gb, loss);
+                      uint16_t *GbT, long ldt, double *loss, hipStream_t s) {
+    mse_kernel<<<1, 256, 0, s>>>(out, y, B, k, G, Gb, GbT, ldt, loss);
     return hipGetLastError();
 }
 

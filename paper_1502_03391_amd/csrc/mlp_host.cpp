@@ -14,17 +14,21 @@ using namespace fjofc;
 struct fjofc_mlp {
     int device = 0;
     int L = 0, maxb = 0, maxw = 0;
+    long ldt = 0;  // leading dimension of the transposed (feature-major) buffers
     std::vector<int> dims;
-    std::vector<size_t> offW, offb;  // offsets into the flat parameter arrays
+    std::vector<size_t> offW, offb;  // offsets into the flat parameter arrays (multiples of 8)
     size_t nparam = 0;
     void *mem = nullptr;
     float *P = nullptr, *G = nullptr, *M1 = nullptr, *M2 = nullptr;
-    uint16_t *P16 = nullptr;
-    std::vector<uint16_t *> H;  // H[l], l = 1..L-1: BF16 activations (maxb x dims[l])
-    std::vector<float *> Z;     // Z[l]: FP32 pre-activations feeding H[l]
-    float *out = nullptr;       // maxb x dims[L]
+    uint16_t *P16 = nullptr;     // BF16 copies; W_l (dims[l] x dims[l+1]) at offW[l]
+    std::vector<uint16_t *> WT;  // WT[l]: BF16 W_l transposed (dims[l+1] x dims[l])
+    std::vector<uint16_t *> H;   // H[l], l = 1..L-1: BF16 activations (maxb x dims[l])
+    std::vector<uint16_t *> HT;  // HT[l]: the same transposed (dims[l] x ldt); HT[0] = x^T
+    std::vector<float *> Z;      // Z[l]: FP32 pre-activations feeding H[l]
+    float *out = nullptr;        // maxb x dims[L]
     float *Gf[2] = {nullptr, nullptr};
     uint16_t *Gb[2] = {nullptr, nullptr};
+    uint16_t *GbT[2] = {nullptr, nullptr};  // BF16 gradients transposed (width x ldt)
     int step = 0;
 };
 
@@ -56,7 +60,18 @@ int check_batch(const fjofc_mlp *n, int B) {
     return FJOFC_OK;
 }
 
-// Forward pass of B rows: H[l+1] = BF16(GELU(H[l] W_l + b_l)), out = last z.
+size_t pad8(size_t x) { return (x + 7) & ~size_t(7); }
+
+// Refresh the transposed BF16 weight copies from P16.
+int refresh_wt(fjofc_mlp *n, hipStream_t s) {
+    for (int l = 0; l < n->L; ++l)
+        HIP_CHECK(launch_transpose16(n->P16 + n->offW[l], n->dims[l + 1], n->dims[l],
+                                     n->dims[l + 1], n->WT[l], n->dims[l], s));
+    return FJOFC_OK;
+}
+
+// Forward pass of B rows: H[l+1] = BF16(GELU(H[l] W_l + b_l)) (and its
+// transpose for the weight gradients), out = last z.
 int forward(fjofc_mlp *n, const uint16_t *x, int B, hipStream_t s) {
     const uint16_t *h = x;
     for (int l = 0; l < n->L; ++l) {
@@ -64,15 +79,16 @@ int forward(fjofc_mlp *n, const uint16_t *x, int B, hipStream_t s) {
         GemmEpi e{};
         e.bias = n->P + n->offb[l];
         e.ldc = o;
+        e.ldt = n->ldt;
         const bool last = (l == n->L - 1);
         if (last) {
             e.outf = n->out;
         } else {
             e.outf = n->Z[l + 1];
             e.outb = n->H[l + 1];
+            e.outbT = n->HT[l + 1];
         }
-        HIP_CHECK(launch_gemm(last ? GEMM_LAST : GEMM_HIDDEN, B, o, in, h, in, 1,
-                              n->P16 + n->offW[l], o, 1, e, s));
+        HIP_CHECK(launch_gemm(last ? GEMM_LAST : GEMM_HIDDEN, B, o, in, h, in, n->WT[l], in, e, s));
         if (!last) h = n->H[l + 1];
     }
     return FJOFC_OK;
@@ -99,31 +115,46 @@ int fjofc_mlp_create(fjofc_ctx *ctx, int L, const int *dims, int max_batch, fjof
     for (int l = 0; l <= L; ++l) n->maxw = std::max(n->maxw, dims[l]);
     for (int l = 0; l < L; ++l) {
         n->offW.push_back(n->nparam);
-        n->nparam += (size_t)dims[l] * dims[l + 1];
+        n->nparam = pad8(n->nparam + (size_t)dims[l] * dims[l + 1]);
         n->offb.push_back(n->nparam);
-        n->nparam += dims[l + 1];
+        n->nparam = pad8(n->nparam + dims[l + 1]);
     }
-    // layout: P, G, M1, M2 (FP32), P16, activations, gradients
+    n->ldt = (long)pad8(max_batch);
+    // layout: P, G, M1, M2 (FP32), P16, WT, activations, gradients
     size_t off = 0;
     const size_t oP = off; off = al(off + 4 * n->nparam);
     const size_t oG = off; off = al(off + 4 * n->nparam);
     const size_t oM1 = off; off = al(off + 4 * n->nparam);
     const size_t oM2 = off; off = al(off + 4 * n->nparam);
+    const size_t zero_end = off;
     const size_t oP16 = off; off = al(off + 2 * n->nparam);
-    std::vector<size_t> oH(L + 1, 0), oZ(L + 1, 0);
-    for (int l = 1; l < L; ++l) {
-        oH[l] = off; off = al(off + 2 * (size_t)max_batch * dims[l]);
-        oZ[l] = off; off = al(off + 4 * (size_t)max_batch * dims[l]);
+    std::vector<size_t> oWT(L, 0);
+    for (int l = 0; l < L; ++l) { oWT[l] = off; off = al(off + 2 * (size_t)dims[l] * dims[l + 1]); }
+    std::vector<size_t> oH(L + 1, 0), oHT(L + 1, 0), oZ(L + 1, 0);
+    for (int l = 0; l < L; ++l) {
+        if (l > 0) {
+            oH[l] = off; off = al(off + 2 * (size_t)max_batch * dims[l]);
+            oZ[l] = off; off = al(off + 4 * (size_t)max_batch * dims[l]);
+        }
+        oHT[l] = off; off = al(off + 2 * (size_t)n->ldt * dims[l]);
     }
     const size_t oOut = off; off = al(off + 4 * (size_t)max_batch * dims[L]);
-    size_t oGf[2], oGb[2];
+    size_t oGf[2], oGb[2], oGbT[2];
     for (int q = 0; q < 2; ++q) {
         oGf[q] = off; off = al(off + 4 * (size_t)max_batch * n->maxw);
         oGb[q] = off; off = al(off + 2 * (size_t)max_batch * n->maxw);
+        oGbT[q] = off; off = al(off + 2 * (size_t)n->ldt * n->maxw);
     }
     if (hipMalloc(&n->mem, off) != hipSuccess) {
         delete n;
         return set_error(FJOFC_ENOMEM, "mlp workspace of %zu bytes", off);
+    }
+    // parameters, gradients and moments start at 0, so the padding between
+    // layers stays 0 through Adam
+    if (hipMemset(n->mem, 0, zero_end) != hipSuccess) {
+        (void)hipFree(n->mem);
+        delete n;
+        return set_error(FJOFC_EHIP, "clearing the mlp workspace failed");
     }
     char *b = static_cast<char *>(n->mem);
     n->P = reinterpret_cast<float *>(b + oP);
@@ -131,16 +162,23 @@ int fjofc_mlp_create(fjofc_ctx *ctx, int L, const int *dims, int max_batch, fjof
     n->M1 = reinterpret_cast<float *>(b + oM1);
     n->M2 = reinterpret_cast<float *>(b + oM2);
     n->P16 = reinterpret_cast<uint16_t *>(b + oP16);
+    n->WT.assign(L, nullptr);
+    for (int l = 0; l < L; ++l) n->WT[l] = reinterpret_cast<uint16_t *>(b + oWT[l]);
     n->H.assign(L + 1, nullptr);
+    n->HT.assign(L + 1, nullptr);
     n->Z.assign(L + 1, nullptr);
-    for (int l = 1; l < L; ++l) {
-        n->H[l] = reinterpret_cast<uint16_t *>(b + oH[l]);
-        n->Z[l] = reinterpret_cast<float *>(b + oZ[l]);
+    for (int l = 0; l < L; ++l) {
+        if (l > 0) {
+            n->H[l] = reinterpret_cast<uint16_t *>(b + oH[l]);
+            n->Z[l] = reinterpret_cast<float *>(b + oZ[l]);
+        }
+        n->HT[l] = reinterpret_cast<uint16_t *>(b + oHT[l]);
     }
     n->out = reinterpret_cast<float *>(b + oOut);
     for (int q = 0; q < 2; ++q) {
         n->Gf[q] = reinterpret_cast<float *>(b + oGf[q]);
         n->Gb[q] = reinterpret_cast<uint16_t *>(b + oGb[q]);
+        n->GbT[q] = reinterpret_cast<uint16_t *>(b + oGbT[q]);
     }
     *out = n;
     return FJOFC_OK;
@@ -166,6 +204,8 @@ int fjofc_mlp_set_params(fjofc_mlp *n, const float *const *W, const float *const
                                  hipMemcpyDeviceToDevice, s));
     }
     HIP_CHECK(launch_to_bf16(n->P, n->P16, (long)n->nparam, s));
+    int rc = refresh_wt(n, s);
+    if (rc) return rc;
     // zero the Adam moments: 0 * finite stays 0 through the update form
     HIP_CHECK(hipMemsetAsync(n->M1, 0, 4 * n->nparam, s));
     HIP_CHECK(hipMemsetAsync(n->M2, 0, 4 * n->nparam, s));
@@ -226,25 +266,28 @@ int fjofc_mlp_backward(fjofc_mlp *n, const unsigned short *x, const float *y, in
     if (rc) return rc;
     const int L = n->L;
     int cur = 0;
-    HIP_CHECK(launch_mse(n->out, y, B, n->dims[L], n->Gf[cur], n->Gb[cur], loss, s));
+    HIP_CHECK(launch_transpose16(x, n->dims[0], B, n->dims[0], n->HT[0], n->ldt, s));
+    HIP_CHECK(launch_mse(n->out, y, B, n->dims[L], n->Gf[cur], n->Gb[cur], n->GbT[cur], n->ldt,
+                         loss, s));
     for (int l = L - 1; l >= 0; --l) {
         const int in = n->dims[l], o = n->dims[l + 1];
-        const uint16_t *h = (l == 0) ? x : n->H[l];
-        // dW_l = h^T g   (in x o), K = B
+        // dW_l = h^T g   (in x o), K = B: both operands feature-major
         GemmEpi e{};
         e.outf = n->G + n->offW[l];
         e.ldc = o;
-        HIP_CHECK(launch_gemm(GEMM_STORE, in, o, B, h, 1, in, n->Gb[cur], o, 1, e, s));
+        HIP_CHECK(launch_gemm(GEMM_STORE, in, o, B, n->HT[l], n->ldt, n->GbT[cur], n->ldt, e, s));
         HIP_CHECK(launch_colsum(n->Gf[cur], B, o, n->G + n->offb[l], s));
         if (l > 0) {
-            // g' = (g W_l^T) * GELU'(z)   (B x in), K = o
+            // g' = (g W_l^T) * GELU'(z)   (B x in), K = o; W_l rows are k-contiguous
             GemmEpi eb{};
             eb.outf = n->Gf[cur ^ 1];
             eb.outb = n->Gb[cur ^ 1];
+            eb.outbT = n->GbT[cur ^ 1];
             eb.Z = n->Z[l];
             eb.ldc = in;
-            HIP_CHECK(launch_gemm(GEMM_BWD, B, in, o, n->Gb[cur], o, 1, n->P16 + n->offW[l], 1, o,
-                                  eb, s));
+            eb.ldt = n->ldt;
+            HIP_CHECK(launch_gemm(GEMM_BWD, B, in, o, n->Gb[cur], o, n->P16 + n->offW[l], o, eb,
+                                  s));
             cur ^= 1;
         }
     }
@@ -273,9 +316,10 @@ int fjofc_mlp_adam(fjofc_mlp *n, float lr, float beta1, float beta2, float eps, 
     n->step += 1;
     const float c1 = (float)(1.0 - std::pow((double)beta1, n->step));
     const float c2 = (float)(1.0 - std::pow((double)beta2, n->step));
+    hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_CHECK(launch_adam(n->P, n->G, n->M1, n->M2, n->P16, (long)n->nparam, lr, beta1, beta2, eps,
-                          c1, c2, static_cast<hipStream_t>(stream)));
-    return FJOFC_OK;
+                          c1, c2, s));
+    return refresh_wt(n, s);
 }
 
 int fjofc_mlp_features(fjofc_ctx *ctx, const float *delta_new, int k, int m, int n,
