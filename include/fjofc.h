@@ -57,9 +57,12 @@ enum {
 enum {
     FJOFC_TOL_NONE = 0, /* run exactly `iters` transforms                  */
     FJOFC_TOL_REL = 1,  /* threshold = tol * sigma_prev                    */
-    FJOFC_TOL_PAPER = 2 /* threshold = tol * C(mn, 2): the normalised
+    FJOFC_TOL_PAPER = 2, /* threshold = tol * C(mn, 2): the normalised
                            stress sigma / C(mn,2) failed to decrease by
                            tol (the paper's experiments use tol = 1e-6)    */
+    FJOFC_TOL_TARGET = 3 /* not a decrease test: stop at the first checkpoint
+                           (t = 0 included) whose sigma(X_t) <= tol, for
+                           measuring the time to reach a given stress      */
 };
 
 #define FJOFC_MAX_M 32  /* modalities per problem                        */
@@ -108,6 +111,22 @@ int fjofc_embed(fjofc_ctx *ctx, const float *const *delta, int m, int n,
                 const double *wmat, int d, float *X, int iters, double tol,
                 int tol_mode, int stress_every, double *stress_hist,
                 fjofc_result *res, void *stream);
+
+/*
+ * Relaxed Guttman transforms, the acceleration of the linear convergence
+ * that the Conclusion proposes (relaxed updates of iterative majorization):
+ *     X_{t+1} = X_t + alpha (Gamma(X_t) - X_t),     0 < alpha < 2,
+ * Gamma being the transform of fjofc_embed (eq:update).  For fixed X_t the
+ * majorizing function of eq:major is a convex quadratic in X minimised at
+ * Gamma(X_t); along this line it is symmetric about alpha = 1, so for every
+ * alpha in (0, 2) it is at most its value at X_t, sigma(X_t), and the raw
+ * stress still does not increase.  alpha = 1 is fjofc_embed exactly; other
+ * arguments and results as for fjofc_embed.                               */
+int fjofc_embed_relaxed(fjofc_ctx *ctx, const float *const *delta, int m,
+                        int n, const double *wmat, int d, float *X, int iters,
+                        double tol, int tol_mode, int stress_every,
+                        double alpha, double *stress_hist, fjofc_result *res,
+                        void *stream);
 
 /* Uniform-weight form of fjofc_embed (eq:W: w_ii = 1, w_ik = w >= 0).     */
 int fjofc_embed_w(fjofc_ctx *ctx, const float *const *delta, int m, int n,

@@ -194,9 +194,15 @@ int orc_stress(int m, int n, int d, const float *delta, const double *wmat,
 /* receives sigma at every evaluated t, NaN elsewhere.                   */
 /* stats: iters_run, converged, sigma, sigma/C(mn,2), fidelity, commens. */
 /* ------------------------------------------------------------------ */
+/* Algorithm 2's loop.  alpha = 1: the Guttman transform X <- Gamma(X).    */
+/* Otherwise the relaxed update X <- X + alpha (Gamma(X) - X) that the      */
+/* Conclusion proposes.  tol_mode 1: stop when sigma_prev - sigma <         */
+/* tol sigma_prev; 2: ... < tol C(mn,2); 3: stop when sigma <= tol (a       */
+/* stress target, tested at t = 0 too).  The tests run at t = 0, every     */
+/* stress_every transforms and at t = iters.                                */
 int orc_embed(int m, int n, int d, const float *delta, const double *wmat,
               double *X, int iters, double tol, int tol_mode, int stress_every,
-              double *hist, double *stats)
+              double alpha, double *hist, double *stats)
 {
     size_t sz = (size_t)m * n * d;
     double *Xn = (double *)malloc(sizeof(double) * sz);
@@ -210,18 +216,27 @@ int orc_embed(int m, int n, int d, const float *delta, const double *wmat,
     if (hist) hist[0] = st[0];
     double last_ck = st[0];
     int run = 0, conv = 0, rc = 0;
-    for (int t = 1; t <= iters; ++t) {
+    if (tol_mode == 3 && tol > 0.0 && st[0] <= tol) conv = 1;
+    for (int t = 1; t <= iters && !conv; ++t) {
         rc = orc_guttman(m, n, d, delta, wmat, X, Xn);
         if (rc) break;
-        memcpy(X, Xn, sizeof(double) * sz);
+        if (alpha == 1.0) {
+            memcpy(X, Xn, sizeof(double) * sz);
+        } else {
+            for (size_t q = 0; q < sz; ++q) X[q] = X[q] + alpha * (Xn[q] - X[q]);
+        }
         run = t;
         int ck = (t % stress_every) == 0;
         if (ck || t == iters) {
             orc_stress(m, n, d, delta, wmat, X, st);
             if (hist) hist[t] = st[0];
             if (ck && tol > 0.0) {
-                double thr = (tol_mode == 2) ? tol * pairs : tol * last_ck;
-                if (last_ck - st[0] < thr) { conv = 1; break; }
+                if (tol_mode == 3) {
+                    if (st[0] <= tol) { conv = 1; break; }
+                } else {
+                    double thr = (tol_mode == 2) ? tol * pairs : tol * last_ck;
+                    if (last_ck - st[0] < thr) { conv = 1; break; }
+                }
             }
             if (ck) last_ck = st[0];
         }

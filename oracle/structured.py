@@ -39,7 +39,7 @@ def lib():
         L.orc_stress.argtypes = [C.c_int, C.c_int, C.c_int, _fp, _dp, _dp, _dp]
         L.orc_embed.argtypes = [C.c_int, C.c_int, C.c_int, _fp, _dp, _dp,
                                 C.c_int, C.c_double, C.c_int, C.c_int,
-                                C.c_void_p, _dp]
+                                C.c_double, C.c_void_p, _dp]
         L.orc_oos_stress.argtypes = [C.c_int, C.c_int, C.c_int, _dp, _dp, _fp, _dp]
         L.orc_oos_stress.restype = C.c_double
         L.orc_oos_step.argtypes = [C.c_int, C.c_int, C.c_int, _dp, _dp, _dp, _fp,
@@ -116,8 +116,10 @@ def stress(delta, wmat, X):
 
 
 def embed(delta, wmat, X0, iters, tol=0.0, tol_mode=1, stress_every=1,
-          want_hist=True):
-    """Algorithm 2's loop from X0.  Returns (X, stats dict, hist)."""
+          want_hist=True, alpha=1.0):
+    """Algorithm 2's loop from X0 (alpha != 1: the relaxed update
+    X + alpha (Gamma(X) - X) of the Conclusion; tol_mode 3: stop once the
+    stress is <= tol).  Returns (X, stats dict, hist)."""
     dl = _stack_delta(delta)
     m, n, _ = dl.shape
     X = _f64(X0).copy()
@@ -125,7 +127,7 @@ def embed(delta, wmat, X0, iters, tol=0.0, tol_mode=1, stress_every=1,
     hist = np.empty(iters + 1) if want_hist else None
     stats = np.empty(6)
     rc = lib().orc_embed(m, n, d, dl, _f64(wmat), X, int(iters), float(tol),
-                         int(tol_mode), int(stress_every),
+                         int(tol_mode), int(stress_every), float(alpha),
                          hist.ctypes.data if want_hist else None, stats)
     if rc:
         raise RuntimeError(f"oracle embed failed ({rc})")

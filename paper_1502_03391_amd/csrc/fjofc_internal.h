@@ -71,6 +71,7 @@ struct InstDesc {
     EmbedState *st;
     double *hist;       // optional: stress history (iters + 1)
     float *X;           // caller's (m n) x d configuration
+    double alpha;       // relaxation: X_{t+1} = X_t + alpha (Gamma(X_t) - X_t)
 };
 
 // One wavefront's work: tile `tile` (I << 16 | J) of modality `mod` of
@@ -151,9 +152,12 @@ hipError_t launch_gemm(int epi, int M, int N, int K, const uint16_t *A, long lda
 hipError_t launch_transpose16(const uint16_t *in, long ld_in, int R, int C, uint16_t *out,
                               long ld_out, hipStream_t s);
 // GbT (optional): the BF16 gradient transposed (k x B, leading dimension ldt).
+// scratch: at least 64 doubles.
 hipError_t launch_mse(const float *out, const float *y, int B, int k, float *G, uint16_t *Gb,
-                      uint16_t *GbT, long ldt, double *loss, hipStream_t s);
-hipError_t launch_colsum(const float *G, int B, int N, float *db, hipStream_t s);
+                      uint16_t *GbT, long ldt, double *loss, double *scratch, hipStream_t s);
+// scratch: at least 16 N doubles.
+hipError_t launch_colsum(const float *G, int B, int N, float *db, double *scratch,
+                         hipStream_t s);
 hipError_t launch_adam(float *p, const float *g, float *m, float *v, uint16_t *p16, long n,
                        float lr, float b1, float b2, float eps, float c1, float c2,
                        hipStream_t s);

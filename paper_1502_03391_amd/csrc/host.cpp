@@ -293,6 +293,7 @@ struct HostInst {
     std::vector<double> Winv, wmat;
     float *X = nullptr;
     int nhist = 0;
+    double alpha = 1.0;
 };
 
 int plan_instance(const float *const *delta, int m, int n, const double *wmat, int d,
@@ -369,6 +370,7 @@ InstDesc make_desc(char *base, const HostInst &h, const size_t offs[9], EmbedSta
     d.st = st;
     d.hist = h.nhist > 0 ? reinterpret_cast<double *>(base + offs[8]) : nullptr;
     d.X = h.X;
+    d.alpha = h.alpha;
     return d;
 }
 
@@ -404,7 +406,7 @@ void fill_result(const EmbedState &st, int m, int n, fjofc_result *res) {
 int check_loop_args(int iters, double &tol, int tol_mode, int stress_every) {
     if (iters < 0) return fail(FJOFC_EINVAL, "iters must be >= 0");
     if (stress_every < 1) return fail(FJOFC_EINVAL, "stress_every must be >= 1");
-    if (tol_mode < FJOFC_TOL_NONE || tol_mode > FJOFC_TOL_PAPER)
+    if (tol_mode < FJOFC_TOL_NONE || tol_mode > FJOFC_TOL_TARGET)
         return fail(FJOFC_EINVAL, "unknown tol_mode %d", tol_mode);
     if (tol_mode == FJOFC_TOL_NONE) tol = 0.0;
     return FJOFC_OK;
@@ -464,7 +466,7 @@ int enqueue_loop(fjofc_ctx *ctx, const InstDesc *insts, int count, int maxm,
 // iters < 0).
 int run_insample(fjofc_ctx *ctx, const float *const *delta, int m, int n,
                  const double *wmat, int d, float *X, int iters, double tol,
-                 int tol_mode, int stress_every, double *stress_hist,
+                 int tol_mode, int stress_every, double alpha, double *stress_hist,
                  fjofc_result *res, hipStream_t s) {
     const bool stress_only = iters < 0;
     if (stress_only) iters = 0;
@@ -474,6 +476,7 @@ int run_insample(fjofc_ctx *ctx, const float *const *delta, int m, int n,
     HostInst h;
     rc = plan_instance(delta, m, n, wmat, d, X, iters + 1, h);
     if (rc) return rc;
+    h.alpha = alpha;
     std::vector<StreamItem> items;
     std::vector<RowItem> rows;
     append_items(0, h, items);
@@ -618,11 +621,20 @@ int fjofc_embed(fjofc_ctx *ctx, const float *const *delta, int m, int n,
                 const double *wmat, int d, float *X, int iters, double tol,
                 int tol_mode, int stress_every, double *stress_hist,
                 fjofc_result *res, void *stream) {
+    return fjofc_embed_relaxed(ctx, delta, m, n, wmat, d, X, iters, tol, tol_mode, stress_every,
+                               1.0, stress_hist, res, stream);
+}
+
+int fjofc_embed_relaxed(fjofc_ctx *ctx, const float *const *delta, int m, int n,
+                        const double *wmat, int d, float *X, int iters, double tol,
+                        int tol_mode, int stress_every, double alpha, double *stress_hist,
+                        fjofc_result *res, void *stream) {
     if (!ctx) return fail(FJOFC_EINVAL, "ctx is NULL");
     if (iters < 0) return fail(FJOFC_EINVAL, "iters must be >= 0");
+    if (!(alpha > 0.0 && alpha < 2.0)) return fail(FJOFC_EINVAL, "alpha=%g outside (0, 2)", alpha);
     DeviceGuard dg(ctx->device);
     return run_insample(ctx, delta, m, n, wmat, d, X, iters, tol, tol_mode,
-                        stress_every, stress_hist, res,
+                        stress_every, alpha, stress_hist, res,
                         static_cast<hipStream_t>(stream));
 }
 
@@ -643,7 +655,7 @@ int fjofc_stress(fjofc_ctx *ctx, const float *const *delta, int m, int n,
     if (!ctx) return fail(FJOFC_EINVAL, "ctx is NULL");
     DeviceGuard dg(ctx->device);
     return run_insample(ctx, delta, m, n, wmat, d, const_cast<float *>(X), -1, 0.0,
-                        FJOFC_TOL_NONE, 1, nullptr, res,
+                        FJOFC_TOL_NONE, 1, 1.0, nullptr, res,
                         static_cast<hipStream_t>(stream));
 }
 

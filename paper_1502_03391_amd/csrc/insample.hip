@@ -436,9 +436,16 @@ __global__ __launch_bounds__(FIN_ROWS) void finalize_kernel(
             bx[q] = wmat[q * m + q] * s;
         }
         float xn[MM];
+        const double alpha = b.alpha;
+        const float *__restrict__ Xin = b.Xs[cur];
         for (int a = 0; a < m; ++a) {
             double v = 0.0;
             for (int q = 0; q < m; ++q) v += Winv[a * m + q] * bx[q];
+            if (alpha != 1.0) {
+                // relaxed update: X_t + alpha (Gamma(X_t) - X_t)
+                const double xt = (double)Xin[((size_t)a * D + k) * npad + j];
+                v = xt + alpha * (v - xt);
+            }
             xn[a] = (float)v;
             Xout[((size_t)a * D + k) * npad + j] = xn[a];
         }
@@ -516,9 +523,15 @@ __global__ __launch_bounds__(RED_BLOCK) void reduce_kernel(
         st->sigma = sigma;
         st->fid = fid;
         st->com = com;
-        if (check && tol > 0.0 && t > 0) {
-            const double thr = (tol_mode == 2) ? tol * 0.5 * mn * (mn - 1.0) : tol * st->last;
-            if (st->last - sigma < thr) {
+        if (check && tol > 0.0) {
+            bool stop;
+            if (tol_mode == 3) {
+                stop = sigma <= tol;  // stress target
+            } else {
+                const double thr = (tol_mode == 2) ? tol * 0.5 * mn * (mn - 1.0) : tol * st->last;
+                stop = t > 0 && st->last - sigma < thr;
+            }
+            if (stop) {
                 st->done = 1;
                 st->converged = 1;
                 st->iters_run = t;

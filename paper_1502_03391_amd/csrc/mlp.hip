@@ -177,18 +177,19 @@ __global__ __launch_bounds__(256) void transpose16_kernel(const uint16_t *__rest
 }
 
 // MSE over the batch and outputs: g = 2 (out - y) / (B k) (FP32 and BF16,
-// and BF16 transposed when GbT is given), loss = mean (out - y)^2 (FP64,
-// fixed-order reduction).
+// and BF16 transposed when GbT is given); each workgroup adds its part of
+// sum (out - y)^2 in FP64 into part[blockIdx.x] (fixed order inside).
+constexpr int MSE_BLOCKS = 64;
 __global__ __launch_bounds__(256) void mse_kernel(const float *__restrict__ out,
                                                   const float *__restrict__ y, int B, int k,
                                                   float *__restrict__ G, uint16_t *__restrict__ Gb,
                                                   uint16_t *__restrict__ GbT, long ldt,
-                                                  double *__restrict__ loss) {
+                                                  double *__restrict__ part) {
     __shared__ double sh[256];
     const long tot = (long)B * k;
     const float sc = 2.0f / (float)tot;
     double s = 0.0;
-    for (long q = threadIdx.x; q < tot; q += 256) {
+    for (long q = blockIdx.x * 256L + threadIdx.x; q < tot; q += 256L * gridDim.x) {
         const float d = out[q] - y[q];
         s += (double)d * d;
         const float g = sc * d;
@@ -203,28 +204,54 @@ __global__ __launch_bounds__(256) void mse_kernel(const float *__restrict__ out,
         if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0 && loss) loss[0] = sh[0] / (double)tot;
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
-// Bias gradient: column sums of G (B x N).  A workgroup owns 64 columns;
-// its 16 row groups (rows r = g, g + 16, ...) accumulate in FP64 and are
-// added in a fixed order, so the result does not depend on scheduling.
-constexpr int CS_COLS = 64, CS_GROUPS = 16;
-__global__ __launch_bounds__(CS_COLS *CS_GROUPS) void colsum_kernel(
-    const float *__restrict__ G, int B, int N, float *__restrict__ db) {
-    __shared__ double part[CS_GROUPS][CS_COLS];
+// loss = (sum of the MSE_BLOCKS parts, in order) / (B k).
+__global__ void mse_finish_kernel(const double *__restrict__ part, long tot,
+                                  double *__restrict__ loss) {
+    double s = 0.0;
+    for (int q = 0; q < MSE_BLOCKS; ++q) s += part[q];
+    loss[0] = s / (double)tot;
+}
+
+// Bias gradient: column sums of G (B x N), two passes.  Pass 1: workgroup
+// (column block of 32, row slice) sums its rows in FP64 with 8 row groups
+// and writes one partial per column and slice; pass 2 adds the slices in
+// order.  The result does not depend on scheduling.
+constexpr int CS_COLS = 32, CS_GROUPS = 8, CS_SLICES = 16;
+__global__ __launch_bounds__(CS_COLS *CS_GROUPS) void colsum_part_kernel(
+    const float *__restrict__ G, int B, int N, double *__restrict__ part) {
+    __shared__ double sh[CS_GROUPS][CS_COLS];
     const int cl = threadIdx.x % CS_COLS, g = threadIdx.x / CS_COLS;
     const int c = blockIdx.x * CS_COLS + cl;
-    double s = 0.0;
-    if (c < N)
-        for (int r = g; r < B; r += CS_GROUPS) s += (double)G[(long)r * N + c];
-    part[g][cl] = s;
+    const int rows = (B + CS_SLICES - 1) / CS_SLICES;
+    const int r0 = blockIdx.y * rows, r1 = min(B, r0 + rows);
+    double s0 = 0.0, s1 = 0.0;
+    if (c < N) {
+        int r = r0 + g;
+        for (; r + CS_GROUPS < r1; r += 2 * CS_GROUPS) {
+            s0 += (double)G[(long)r * N + c];
+            s1 += (double)G[(long)(r + CS_GROUPS) * N + c];
+        }
+        if (r < r1) s0 += (double)G[(long)r * N + c];
+    }
+    sh[g][cl] = s0 + s1;
     __syncthreads();
     if (g == 0 && c < N) {
         double t = 0.0;
-        for (int q = 0; q < CS_GROUPS; ++q) t += part[q][cl];
-        db[c] = (float)t;
+        for (int q = 0; q < CS_GROUPS; ++q) t += sh[q][cl];
+        part[(long)blockIdx.y * N + c] = t;
     }
+}
+
+__global__ void colsum_finish_kernel(const double *__restrict__ part, int N,
+                                     float *__restrict__ db) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= N) return;
+    double t = 0.0;
+    for (int q = 0; q < CS_SLICES; ++q) t += part[(long)q * N + c];
+    db[c] = (float)t;
 }
 
 // Adam with bias correction on the FP32 masters; refreshes the BF16 copy.
@@ -322,14 +349,22 @@ hipError_t launch_transpose16(const uint16_t *in, long ld_in, int R, int C, uint
 }
 
 hipError_t launch_mse(const float *out, const float *y, int B, int k, float *G, uint16_t *Gb,
-                      uint16_t *GbT, long ldt, double *loss, hipStream_t s) {
-    mse_kernel<<<1, 256, 0, s>>>(out, y, B, k, G, Gb, GbT, ldt, loss);
+                      uint16_t *GbT, long ldt, double *loss, double *scratch, hipStream_t s) {
+    mse_kernel<<<MSE_BLOCKS, 256, 0, s>>>(out, y, B, k, G, Gb, GbT, ldt, scratch);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !loss) return e;
+    mse_finish_kernel<<<1, 1, 0, s>>>(scratch, (long)B * k, loss);
     return hipGetLastError();
 }
 
-hipError_t launch_colsum(const float *G, int B, int N, float *db, hipStream_t s) {
+hipError_t launch_colsum(const float *G, int B, int N, float *db, double *scratch,
+                         hipStream_t s) {
     if (N <= 0) return hipSuccess;
-    colsum_kernel<<<(unsigned)((N + CS_COLS - 1) / CS_COLS), CS_COLS * CS_GROUPS, 0, s>>>(G, B, N, db);
+    const dim3 grid((unsigned)((N + CS_COLS - 1) / CS_COLS), CS_SLICES);
+    colsum_part_kernel<<<grid, CS_COLS * CS_GROUPS, 0, s>>>(G, B, N, scratch);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    colsum_finish_kernel<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(scratch, N, db);
     return hipGetLastError();
 }
 

@@ -29,6 +29,7 @@ struct fjofc_mlp {
     float *Gf[2] = {nullptr, nullptr};
     uint16_t *Gb[2] = {nullptr, nullptr};
     uint16_t *GbT[2] = {nullptr, nullptr};  // BF16 gradients transposed (width x ldt)
+    double *scratch = nullptr;              // reduction partials (16 maxw + 64 doubles)
     int step = 0;
 };
 
@@ -145,6 +146,7 @@ int fjofc_mlp_create(fjofc_ctx *ctx, int L, const int *dims, int max_batch, fjof
         oGb[q] = off; off = al(off + 2 * (size_t)max_batch * n->maxw);
         oGbT[q] = off; off = al(off + 2 * (size_t)n->ldt * n->maxw);
     }
+    const size_t oScr = off; off = al(off + 8 * (16 * (size_t)n->maxw + 64));
     if (hipMalloc(&n->mem, off) != hipSuccess) {
         delete n;
         return set_error(FJOFC_ENOMEM, "mlp workspace of %zu bytes", off);
@@ -180,6 +182,7 @@ int fjofc_mlp_create(fjofc_ctx *ctx, int L, const int *dims, int max_batch, fjof
         n->Gb[q] = reinterpret_cast<uint16_t *>(b + oGb[q]);
         n->GbT[q] = reinterpret_cast<uint16_t *>(b + oGbT[q]);
     }
+    n->scratch = reinterpret_cast<double *>(b + oScr);
     *out = n;
     return FJOFC_OK;
 }
@@ -268,7 +271,7 @@ int fjofc_mlp_backward(fjofc_mlp *n, const unsigned short *x, const float *y, in
     int cur = 0;
     HIP_CHECK(launch_transpose16(x, n->dims[0], B, n->dims[0], n->HT[0], n->ldt, s));
     HIP_CHECK(launch_mse(n->out, y, B, n->dims[L], n->Gf[cur], n->Gb[cur], n->GbT[cur], n->ldt,
-                         loss, s));
+                         loss, n->scratch, s));
     for (int l = L - 1; l >= 0; --l) {
         const int in = n->dims[l], o = n->dims[l + 1];
         // dW_l = h^T g   (in x o), K = B: both operands feature-major
@@ -276,7 +279,7 @@ int fjofc_mlp_backward(fjofc_mlp *n, const unsigned short *x, const float *y, in
         e.outf = n->G + n->offW[l];
         e.ldc = o;
         HIP_CHECK(launch_gemm(GEMM_STORE, in, o, B, n->HT[l], n->ldt, n->GbT[cur], n->ldt, e, s));
-        HIP_CHECK(launch_colsum(n->Gf[cur], B, o, n->G + n->offb[l], s));
+        HIP_CHECK(launch_colsum(n->Gf[cur], B, o, n->G + n->offb[l], n->scratch, s));
         if (l > 0) {
             // g' = (g W_l^T) * GELU'(z)   (B x in), K = o; W_l rows are k-contiguous
             GemmEpi eb{};

@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfjofc.so")
 
 FJOFC_OK = 0
-FJOFC_TOL_NONE, FJOFC_TOL_REL, FJOFC_TOL_PAPER = 0, 1, 2
+FJOFC_TOL_NONE, FJOFC_TOL_REL, FJOFC_TOL_PAPER, FJOFC_TOL_TARGET = 0, 1, 2, 3
 FJOFC_MAX_M = 32
 FJOFC_MAX_D = 8
 
@@ -28,7 +28,7 @@ EXPORTS = ["fjofc_create", "fjofc_destroy", "fjofc_last_error", "fjofc_strerror"
            "fjofc_mlp_create", "fjofc_mlp_destroy", "fjofc_mlp_set_params",
            "fjofc_mlp_get_params", "fjofc_mlp_forward", "fjofc_mlp_backward",
            "fjofc_mlp_get_grads", "fjofc_mlp_adam", "fjofc_mlp_features",
-           "fjofc_mlp_predict_start", "fjofc_oos_nearest_start"]
+           "fjofc_mlp_predict_start", "fjofc_oos_nearest_start", "fjofc_embed_relaxed"]
 
 
 class FjofcResult(C.Structure):
@@ -90,6 +90,9 @@ def lib():
         L.fjofc_embed.argtypes = [vp, C.POINTER(vp), ip, ip, C.POINTER(dp), ip, vp,
                                   ip, dp, ip, ip, C.POINTER(dp),
                                   C.POINTER(FjofcResult), vp]
+        L.fjofc_embed_relaxed.argtypes = [vp, C.POINTER(vp), ip, ip, C.POINTER(dp), ip, vp,
+                                          ip, dp, ip, ip, dp, C.POINTER(dp),
+                                          C.POINTER(FjofcResult), vp]
         L.fjofc_embed_w.argtypes = [vp, C.POINTER(vp), ip, ip, dp, ip, vp,
                                     ip, dp, ip, ip, C.POINTER(dp),
                                     C.POINTER(FjofcResult), vp]
@@ -172,10 +175,12 @@ class Context:
 
 def fjofc_embed(ctx: Context, delta: Sequence, wmat, X, iters: int,
                 tol: float = 0.0, tol_mode: int = FJOFC_TOL_REL,
-                stress_every: int = 1, want_hist: bool = False, stream=None):
+                stress_every: int = 1, want_hist: bool = False, stream=None,
+                alpha: float = 1.0):
     """In-sample fJOFC.  delta: m CUDA float32 n x n tensors; X: CUDA
-    float32 (m n) x d tensor, X0 in, result out.  Returns (result dict,
-    stress history or None)."""
+    float32 (m n) x d tensor, X0 in, result out; alpha != 1 runs the relaxed
+    transforms (fjofc_embed_relaxed).  Returns (result dict, stress history
+    or None)."""
     import torch
     m = len(delta)
     n = int(delta[0].shape[0])
@@ -185,10 +190,16 @@ def fjofc_embed(ctx: Context, delta: Sequence, wmat, X, iters: int,
     res = FjofcResult()
     hist = np.empty(iters + 1) if want_hist else None
     hp = hist.ctypes.data_as(C.POINTER(C.c_double)) if want_hist else None
-    _check(lib().fjofc_embed(ctx.handle, ptrs, m, n, wp, d,
-                             _dev_ptr(X, torch.float32, "X"), int(iters),
-                             float(tol), int(tol_mode), int(stress_every), hp,
-                             C.byref(res), _stream_ptr(stream)))
+    if alpha == 1.0:
+        _check(lib().fjofc_embed(ctx.handle, ptrs, m, n, wp, d,
+                                 _dev_ptr(X, torch.float32, "X"), int(iters),
+                                 float(tol), int(tol_mode), int(stress_every), hp,
+                                 C.byref(res), _stream_ptr(stream)))
+    else:
+        _check(lib().fjofc_embed_relaxed(ctx.handle, ptrs, m, n, wp, d,
+                                         _dev_ptr(X, torch.float32, "X"), int(iters),
+                                         float(tol), int(tol_mode), int(stress_every),
+                                         float(alpha), hp, C.byref(res), _stream_ptr(stream)))
     return res.as_dict(), hist
 
 

@@ -192,3 +192,49 @@ def test_invalid_arguments_are_rejected(ctx):
         fjofc.fjofc_embed(ctx, dd, wmat, _dev(np.zeros((100, 9))), 1)
     with pytest.raises(fjofc.FjofcError):
         fjofc.fjofc_embed(ctx, dd, wmat, _dev(X0), 1, stress_every=0)
+
+
+@pytest.mark.parametrize("alpha", [0.6, 1.5, 1.9])
+def test_relaxed_transforms_parity(ctx, alpha):
+    """fjofc_embed_relaxed against the oracle's relaxed loop, general W and a
+    ragged n; stress history non-increasing (R16's FP32 slack)."""
+    m, n, d = 3, 517, 3
+    wmat = _general_wmat(m, seed=21)
+    delta, _, X0 = _problem(22, m, n, d, wmat=wmat)
+    Xo, ro, ho = orc.embed(delta, wmat, X0, 40, stress_every=4, alpha=alpha)
+    Xg, rg, hg = _gpu_embed(ctx, delta, wmat, X0, 40, stress_every=4, alpha=alpha,
+                            want_hist=True)
+    assert rg["iters_run"] == 40
+    assert rg["stress"] == pytest.approx(ro["stress"], rel=1e-5)
+    assert _rel_fro(Xg, Xo) <= 1e-4
+    h = hg[~np.isnan(hg)]
+    assert np.all(np.diff(h) <= 1e-6 * h[:-1])
+
+
+def test_target_stop_matches_oracle(ctx):
+    """FJOFC_TOL_TARGET: stop at the first checkpoint with sigma <= tol, for
+    plain and relaxed transforms; at t = 0 when X0 already meets it."""
+    m, n, d = 2, 300, 2
+    delta, wmat, X0 = _problem(23, m, n, d)
+    _, r60, hist = orc.embed(delta, wmat, X0, 60, tol_mode=0)
+    target = r60["stress"] * (1 + 1e-3)
+    for alpha in (1.0, 1.9):
+        Xo, ro, ho = orc.embed(delta, wmat, X0, 200, tol=target, tol_mode=3, alpha=alpha)
+        Xg, rg, _ = _gpu_embed(ctx, delta, wmat, X0, 200, tol=target, tol_mode=3, alpha=alpha)
+        t = ro["iters_run"]
+        assert ro["converged"] == 1 and 0 < t < 200
+        # decisions within FP32 noise of the target are not compared
+        if ho[t - 1] > target * (1 + 1e-5) and ho[t] < target * (1 - 1e-5):
+            assert rg["iters_run"] == t and rg["converged"] == 1
+            assert _rel_fro(Xg, Xo) <= 1e-4
+    Xg, rg, _ = _gpu_embed(ctx, delta, wmat, X0, 50, tol=hist[0] * 2, tol_mode=3)
+    assert rg["iters_run"] == 0 and rg["converged"] == 1
+    np.testing.assert_array_equal(Xg, X0.astype(np.float64))
+
+
+def test_relaxation_factor_is_validated(ctx):
+    delta, wmat, X0 = _problem(24, 2, 40, 2)
+    dd = [_dev(x) for x in delta]
+    for alpha in (0.0, 2.0, -1.0, float("nan")):
+        with pytest.raises(fjofc.FjofcError):
+            fjofc.fjofc_embed(ctx, dd, wmat, _dev(X0), 1, alpha=alpha)

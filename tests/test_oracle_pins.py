@@ -420,3 +420,59 @@ def test_nearest_start_brute_force():
                 if best is None or dnew[o, i, j] < best:
                     best, bj = dnew[o, i, j], j
             assert np.array_equal(Y[o, i], X[i * n + bj])
+
+
+# ---------------------------------------------------------- relaxed updates
+def _majorizer(X, Y, D, W, L):
+    """eq:major's majorizing function at X for the support point Y:
+    sum W Delta^2 + tr X'LX - 2 tr X'B(Y)Y (it equals sigma at X = Y)."""
+    iu = np.triu_indices(X.shape[0], 1)
+    BY = dense.B_matrix(Y, D, W) @ Y
+    return (W[iu] * D[iu] ** 2).sum() + np.trace(X.T @ L @ X) - 2 * np.trace(X.T @ BY)
+
+
+@pytest.mark.parametrize("alpha", [0.4, 1.3, 1.9])
+def test_relaxed_step_lies_on_symmetric_majorizer(alpha):
+    """The Conclusion's relaxed update X + alpha (Gamma(X) - X): the oracle's
+    step must sit where the dense majorizer of eq:major takes the same value
+    as at 2 - alpha (the quadratic is symmetric about its minimiser
+    Gamma(X)), below sigma(X), and above the new stress."""
+    m, n, d = 2, 14, 2
+    delta, wmat, X0 = _problem(61, m, n, d)
+    D = dense.omnibus_delta(delta)
+    W = dense.omnibus_weights(wmat, n)
+    L = dense.laplacian(W)
+    X1, _, _ = orc.embed(delta, wmat, X0, 1, tol_mode=0, alpha=alpha)
+    X1m, _, _ = orc.embed(delta, wmat, X0, 1, tol_mode=0, alpha=2.0 - alpha)
+    ga, gb = _majorizer(X1, X0, D, W, L), _majorizer(X1m, X0, D, W, L)
+    s0 = dense.stress(X0, D, W)
+    assert ga == pytest.approx(gb, rel=1e-11)
+    assert ga <= s0 * (1 + 1e-12)
+    assert dense.stress(X1, D, W) <= ga * (1 + 1e-12)
+    # the two steps straddle Gamma(X0): their mean is the plain transform
+    G, _, _ = orc.embed(delta, wmat, X0, 1, tol_mode=0)
+    np.testing.assert_allclose(0.5 * (X1 + X1m), G, rtol=0, atol=1e-12 * np.abs(G).max())
+
+
+def test_relaxed_stress_monotone():
+    delta, wmat, X0 = _problem(62, 3, 30, 2)
+    _, _, hist = orc.embed(delta, wmat, X0, 100, alpha=1.9)
+    assert np.all(np.diff(hist) <= 1e-12 * hist[:-1])
+
+
+def test_target_mode_and_relaxed_reach_target_sooner():
+    """tol_mode 3 stops at the first checkpoint whose stress is <= tol; the
+    relaxed transforms reach the plain run's 200-transform stress in fewer
+    transforms (the acceleration the Conclusion asks for)."""
+    delta, wmat, X0 = _problem(63, 2, 60, 2, lat=3, sigma=0.1)
+    _, r200, hist = orc.embed(delta, wmat, X0, 200, tol_mode=0)
+    target = r200["stress"] * (1 + 1e-4)
+    _, rp, hp = orc.embed(delta, wmat, X0, 400, tol=target, tol_mode=3, stress_every=1)
+    first = int(np.argmax(hist <= target))
+    assert rp["converged"] == 1 and rp["iters_run"] == first
+    _, rr, _ = orc.embed(delta, wmat, X0, 400, tol=target, tol_mode=3, stress_every=1, alpha=1.9)
+    assert rr["converged"] == 1 and rr["stress"] <= target
+    assert rr["iters_run"] < 0.8 * rp["iters_run"]
+    # a target above the start's stress stops before any transform
+    _, r0, _ = orc.embed(delta, wmat, X0, 50, tol=hist[0] * 2, tol_mode=3)
+    assert r0["iters_run"] == 0 and r0["converged"] == 1
