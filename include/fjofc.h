@@ -128,6 +128,29 @@ int fjofc_embed_relaxed(fjofc_ctx *ctx, const float *const *delta, int m,
                         double alpha, double *stress_hist, fjofc_result *res,
                         void *stream);
 
+/*
+ * The paper's initialisation X_0 for fjofc_embed (Algorithm 2's first
+ * lines, with Algorithm 1 step 1's classical MDS):
+ *   xi_0 = cMDS of the mean dissimilarity (sum_i Delta_i) / m,
+ *   xi_i = cMDS of Delta_i,
+ *   X^(i)_0 = xi_i Q_i, Q_i the orthogonal Procrustes rotation of xi_i onto
+ *             xi_0 (Q_i maximises tr(Q^T xi_i^T xi_0): the polar factor of
+ *             xi_i^T xi_0; the printed U V^T, from the SVD of xi_0^T xi_i,
+ *             is its transpose).
+ * cMDS of A: the d largest eigenpairs (lambda, u) of
+ * P = -1/2 (I - J/n)(A o A)(I - J/n); X = [u_1..u_d] diag(max(lambda,0))^(1/2)
+ * (centred).  They are computed by `iters` steps of subspace iteration on
+ * a block of K >= max(2d, d + 3) vectors (each step streams the m Delta_i
+ * once for the mean and once for its own Delta_i), then Rayleigh-Ritz.
+ *   delta, m, n, d  as for fjofc_embed (d <= FJOFC_MAX_D).
+ *   X               device (m*n) x d FP32, written.
+ *   iters           subspace-iteration steps per matrix, 1..10000.
+ *   eigvals         optional host (m + 1) x d: the d largest Ritz values of
+ *                   P for the mean, then for each Delta_i.
+ * Synchronises `stream`.                                                  */
+int fjofc_init_cmds(fjofc_ctx *ctx, const float *const *delta, int m, int n,
+                    int d, float *X, int iters, double *eigvals, void *stream);
+
 /* Uniform-weight form of fjofc_embed (eq:W: w_ii = 1, w_ik = w >= 0).     */
 int fjofc_embed_w(fjofc_ctx *ctx, const float *const *delta, int m, int n,
                   double w, int d, float *X, int iters, double tol,

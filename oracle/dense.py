@@ -151,3 +151,41 @@ def nearest_start(X: np.ndarray, dnew: np.ndarray) -> np.ndarray:
             j = int(np.argmin(dnew[o, i]))
             Y[o, i] = X[i * n + j]
     return Y
+
+
+def cmds(D: np.ndarray, d: int):
+    """Classical MDS (Algorithm 1 step 1): the d largest eigenpairs of
+    P = -1/2 J (D o D) J, J = I - 11^T/n (numpy's eigh); returns
+    X = U diag(max(lambda, 0))^(1/2) and the eigenvalues (descending)."""
+    D = np.asarray(D, dtype=np.float64)
+    n = D.shape[0]
+    J = np.eye(n) - 1.0 / n
+    P = -0.5 * J @ (D * D) @ J
+    w, U = np.linalg.eigh(0.5 * (P + P.T))
+    idx = np.argsort(w)[::-1][:d]
+    return U[:, idx] * np.sqrt(np.maximum(w[idx], 0.0)), w[idx]
+
+
+def procrustes_rotation(xi: np.ndarray, xi0: np.ndarray) -> np.ndarray:
+    """Orthogonal Q minimising ||xi Q - xi0||_F: with xi^T xi0 = U S V^T,
+    Q = U V^T (numpy's SVD).  Algorithm 2 prints xi_i U V^T with U S V^T the
+    SVD of xi_0^T xi_i, which is the transpose of this Q."""
+    U, _, Vt = np.linalg.svd(xi.T @ xi0)
+    return U @ Vt
+
+
+def paper_init(delta, d: int):
+    """Algorithm 2's start: cMDS of the mean dissimilarity (xi_0), cMDS of
+    each Delta_i centred, Procrustes fit onto xi_0; stacked modality-major.
+    Returns (X0, eigenvalues (m + 1) x d)."""
+    m = len(delta)
+    Dm = sum(np.asarray(x, dtype=np.float64) for x in delta) / m
+    xi0, e0 = cmds(Dm, d)
+    xi0 = xi0 - xi0.mean(axis=0)
+    blocks, eigs = [], [e0]
+    for x in delta:
+        xi, e = cmds(x, d)
+        xi = xi - xi.mean(axis=0)
+        blocks.append(xi @ procrustes_rotation(xi, xi0))
+        eigs.append(e)
+    return np.vstack(blocks), np.array(eigs)

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+struct fjofc_ctx;
+
 namespace fjofc {
 
 constexpr int WAVE = 64;
@@ -134,6 +136,19 @@ hipError_t launch_oos(const OOSArgs &a, double *colsum, hipStream_t s);
 hipError_t launch_nearest(const float *X, int m, int n, int d, const float *dnew, int k,
                           float *Y, hipStream_t s);
 
+// ---- classical MDS initialisation (cmds.hip) --------------------------
+// W (n x K) = (A o A) V with A = scale * sum of the nsrc matrices in dp
+// (n x n row-major); V, W row-major with K in {4, 8, 12, 16} columns.
+hipError_t launch_sqprod(const DeltaPtrs &dp, int nsrc, float scale, int n, int K,
+                         const float *V, float *W, hipStream_t s);
+// out (ka x kb, FP64) = A^T B over n rows (B == nullptr: column sums of A).
+hipError_t launch_cross(const float *A, int lda, int ka, const float *B, int ldb, int kb, int n,
+                        double *out, hipStream_t s);
+// out[j][c] = sum_a (in[j][a] - mu[a]) M[a][c] for c < ncol, 0 for
+// ncol <= c < ldo_pad; mu optional.
+hipError_t launch_apply(const float *in, int ldi, int nin, const double *mu, const double *M,
+                        int ncol, int n, float *out, int ldo, int ldo_pad, hipStream_t s);
+
 // ---- warm-start network (mlp.hip) -------------------------------------
 enum { GEMM_HIDDEN = 0, GEMM_LAST = 1, GEMM_BWD = 2, GEMM_STORE = 3 };
 struct GemmEpi {
@@ -171,5 +186,11 @@ hipError_t launch_features(const float *dnew, int k, int m, int n, const int *lm
 
 // Records the calling thread's error message (host.cpp); returns `code`.
 int set_error(int code, const char *fmt, ...);
+// Context services for entry points outside host.cpp: its device, its
+// device workspace (grown to at least `bytes`; contents not preserved) and
+// its pinned host staging buffer.
+int ctx_device(const fjofc_ctx *ctx);
+int ctx_workspace(fjofc_ctx *ctx, size_t bytes, void **ws);
+int ctx_pinned(fjofc_ctx *ctx, size_t bytes, void **p);
 
 }  // namespace fjofc

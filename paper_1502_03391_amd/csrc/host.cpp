@@ -528,6 +528,22 @@ int run_insample(fjofc_ctx *ctx, const float *const *delta, int m, int n,
 
 }  // namespace
 
+int fjofc::ctx_device(const fjofc_ctx *ctx) { return ctx->device; }
+
+int fjofc::ctx_workspace(fjofc_ctx *ctx, size_t bytes, void **ws) {
+    const int rc = ensure_ws(ctx, bytes);
+    if (rc) return rc;
+    *ws = ctx->ws;
+    return FJOFC_OK;
+}
+
+int fjofc::ctx_pinned(fjofc_ctx *ctx, size_t bytes, void **p) {
+    const int rc = ensure_pinned(ctx, bytes);
+    if (rc) return rc;
+    *p = ctx->pinned;
+    return FJOFC_OK;
+}
+
 int fjofc::set_error(int code, const char *fmt, ...) {
     char buf[512];
     va_list ap;

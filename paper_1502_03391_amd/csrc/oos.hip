@@ -24,6 +24,7 @@
 // leave the live list, so later transforms stream only live objects.  The
 // fidelity term is accumulated only on transforms whose stress is used.
 #include "fjofc_internal.h"
+#include "wave_ops.h"
 #include <float.h>
 
 namespace fjofc {
@@ -32,54 +33,8 @@ namespace {
 constexpr int OOS_BLOCK = 256;
 constexpr int OOS_WAVES = OOS_BLOCK / WAVE;
 
-constexpr int DPP_QP_XOR1 = 0xB1;  // quad_perm [1,0,3,2]
-constexpr int DPP_QP_XOR2 = 0x4E;  // quad_perm [2,3,0,1]
-constexpr int DPP_ROW_HALF_MIRROR = 0x141;
-constexpr int DPP_ROW_ROR8 = 0x128;
 constexpr int BUF_DWORD3 = 0x00020000;  // raw 32-bit buffer, gfx9 family
-
-template <int CTRL>
-__device__ __forceinline__ float dpp(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-
-// Lanes 0-31 return a summed over both 32-lane halves, lanes 32-63 return b.
-__device__ __forceinline__ float swap32_add(float a, float b) {
-    auto s = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
-    return __uint_as_float(s[0]) + __uint_as_float(s[1]);
-}
-// Even 16-lane rows return a summed over the row pair, odd rows return b.
-__device__ __forceinline__ float swap16_add(float a, float b) {
-    auto s = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
-    return __uint_as_float(s[0]) + __uint_as_float(s[1]);
-}
-
-// Reduce V values (V % 8 == 0) over the 64 lanes.  Afterwards c[r] in every
-// lane of an aligned group of 8 lanes holds the wave total of value
-//   r + bit3 V/8 + bit4 V/4 + bit5 V/2     (bits of the lane index).
-template <int V>
-__device__ __forceinline__ void reduce_scatter8(float (&p)[V], float (&c)[V / 8], int lane) {
-    static_assert(V % 8 == 0, "V is a multiple of 8");
-    float a[V / 2];
-#pragma unroll
-    for (int r = 0; r < V / 2; ++r) a[r] = swap32_add(p[r], p[r + V / 2]);
-    float b[V / 4];
-#pragma unroll
-    for (int r = 0; r < V / 4; ++r) b[r] = swap16_add(a[r], a[r + V / 4]);
-    const bool b3 = lane & 8;
-#pragma unroll
-    for (int r = 0; r < V / 8; ++r) {
-        const float send = b3 ? b[r] : b[r + V / 8];
-        const float keep = b3 ? b[r + V / 8] : b[r];
-        c[r] = keep + dpp<DPP_ROW_ROR8>(send);
-    }
-#pragma unroll
-    for (int r = 0; r < V / 8; ++r) {
-        c[r] += dpp<DPP_QP_XOR1>(c[r]);
-        c[r] += dpp<DPP_QP_XOR2>(c[r]);
-        c[r] += dpp<DPP_ROW_HALF_MIRROR>(c[r]);
-    }
-}
+using wave::reduce_scatter8;
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const float *p, int bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(p), (short)0, bytes, BUF_DWORD3);
@@ -198,8 +153,7 @@ __device__ __forceinline__ void stream_modality(const OOSArgs &a, int i, int o0,
     float c[VL / 8];
     reduce_scatter8<VL>(p, c, lane);
     if ((lane & 7) == 0) {
-        const int base = ((lane >> 3) & 1) * (VL / 8) + ((lane >> 4) & 1) * (VL / 4) +
-                         ((lane >> 5) & 1) * (VL / 2);
+        const int base = wave::scatter8_base(lane, VL);
 #pragma unroll
         for (int r = 0; r < VL / 8; ++r) dst[base + r] = c[r];
     }

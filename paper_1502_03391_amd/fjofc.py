@@ -28,7 +28,8 @@ EXPORTS = ["fjofc_create", "fjofc_destroy", "fjofc_last_error", "fjofc_strerror"
            "fjofc_mlp_create", "fjofc_mlp_destroy", "fjofc_mlp_set_params",
            "fjofc_mlp_get_params", "fjofc_mlp_forward", "fjofc_mlp_backward",
            "fjofc_mlp_get_grads", "fjofc_mlp_adam", "fjofc_mlp_features",
-           "fjofc_mlp_predict_start", "fjofc_oos_nearest_start", "fjofc_embed_relaxed"]
+           "fjofc_mlp_predict_start", "fjofc_oos_nearest_start", "fjofc_embed_relaxed",
+           "fjofc_init_cmds"]
 
 
 class FjofcResult(C.Structure):
@@ -93,6 +94,7 @@ def lib():
         L.fjofc_embed_relaxed.argtypes = [vp, C.POINTER(vp), ip, ip, C.POINTER(dp), ip, vp,
                                           ip, dp, ip, ip, dp, C.POINTER(dp),
                                           C.POINTER(FjofcResult), vp]
+        L.fjofc_init_cmds.argtypes = [vp, C.POINTER(vp), ip, ip, ip, vp, ip, C.POINTER(dp), vp]
         L.fjofc_embed_w.argtypes = [vp, C.POINTER(vp), ip, ip, dp, ip, vp,
                                     ip, dp, ip, ip, C.POINTER(dp),
                                     C.POINTER(FjofcResult), vp]
@@ -201,6 +203,24 @@ def fjofc_embed(ctx: Context, delta: Sequence, wmat, X, iters: int,
                                          float(tol), int(tol_mode), int(stress_every),
                                          float(alpha), hp, C.byref(res), _stream_ptr(stream)))
     return res.as_dict(), hist
+
+
+def fjofc_init_cmds(ctx: Context, delta: Sequence, X, iters: int = 20, stream=None):
+    """The paper's start X0: cMDS of the mean dissimilarity, cMDS of each
+    Delta_i, Procrustes fit of each onto the first.  X: CUDA float32
+    (m n) x d, written.  Returns the (m + 1) x d largest Ritz values."""
+    import torch
+    m = len(delta)
+    n = int(delta[0].shape[0])
+    d = int(X.shape[1])
+    if tuple(X.shape) != (m * n, d):
+        raise ValueError(f"X must be {m * n} x d")
+    ptrs = (C.c_void_p * m)(*[_dev_ptr(t, torch.float32, "delta") for t in delta])
+    eig = np.empty((m + 1, d))
+    _check(lib().fjofc_init_cmds(ctx.handle, ptrs, m, n, d, _dev_ptr(X, torch.float32, "X"),
+                                 int(iters), eig.ctypes.data_as(C.POINTER(C.c_double)),
+                                 _stream_ptr(stream)))
+    return eig
 
 
 def fjofc_stress(ctx: Context, delta: Sequence, wmat, X, stream=None):

@@ -476,3 +476,52 @@ def test_target_mode_and_relaxed_reach_target_sooner():
     # a target above the start's stress stops before any transform
     _, r0, _ = orc.embed(delta, wmat, X0, 50, tol=hist[0] * 2, tol_mode=3)
     assert r0["iters_run"] == 0 and r0["converged"] == 1
+
+
+# ------------------------------------------------- the paper's initialisation
+def test_cmds_recovers_euclidean_configuration():
+    """Algorithm 1 step 1 on exact Euclidean distances of n points in R^d
+    gives a configuration with the same distances, and P's eigenvalues are
+    those of the centred Gram Y^T Y."""
+    rng = np.random.default_rng(71)
+    Y = rng.standard_normal((40, 3)) * [3.0, 2.0, 1.0]
+    D = dense.distances(Y)
+    X, lam = dense.cmds(D, 3)
+    np.testing.assert_allclose(dense.distances(X), D, rtol=0, atol=1e-10 * D.max())
+    Yc = Y - Y.mean(axis=0)
+    np.testing.assert_allclose(lam, np.sort(np.linalg.eigvalsh(Yc.T @ Yc))[::-1], rtol=1e-10)
+    np.testing.assert_allclose(X.mean(axis=0), 0.0, atol=1e-10)
+
+
+def test_procrustes_reading_recovers_rotation():
+    """R13: the rotation that fits xi onto xi_0 = xi R^T is R; the printed
+    U V^T (SVD of xi_0^T xi) is its transpose and does not fit."""
+    rng = np.random.default_rng(72)
+    xi0 = rng.standard_normal((30, 3))
+    R, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    xi = xi0 @ R.T
+    Q = dense.procrustes_rotation(xi, xi0)
+    np.testing.assert_allclose(xi @ Q, xi0, atol=1e-12)
+    U, _, Vt = np.linalg.svd(xi0.T @ xi)
+    assert np.linalg.norm(xi @ (U @ Vt) - xi0) > 1e-3 * np.linalg.norm(xi0)
+
+
+def test_paper_init_of_congruent_views_has_zero_stress():
+    """When every Delta_i is the distance matrix of one configuration
+    (rotated and translated copies), all blocks of X_0 coincide and the JOFC
+    stress of X_0 vanishes."""
+    rng = np.random.default_rng(73)
+    Y = rng.standard_normal((25, 2)) * [2.0, 1.0]
+    views = []
+    for i in range(3):
+        R, _ = np.linalg.qr(rng.standard_normal((2, 2)))
+        views.append(Y @ R + rng.standard_normal(2))
+    delta = [dense.distances(v).astype(np.float32) for v in views]
+    X0, eig = dense.paper_init(delta, 2)
+    n = 25
+    for i in range(1, 3):
+        np.testing.assert_allclose(X0[i * n:(i + 1) * n], X0[:n], atol=1e-5)
+    s, _, _ = orc.stress(delta, gen.uniform_wmat(3, 0.5), X0)
+    total = sum((x.astype(np.float64) ** 2).sum() / 2 for x in delta)
+    assert s <= 1e-9 * total
+    np.testing.assert_allclose(eig[1:], np.repeat(eig[:1], 3, axis=0), rtol=1e-6)
