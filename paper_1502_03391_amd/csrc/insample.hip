@@ -385,28 +385,33 @@ __device__ __forceinline__ double block_sum_d(double v, double *sh) {
     return s;
 }
 
-// Sum of the slots [q0, q1) of one partial column (stride `slot` floats),
-// four independent FP64 accumulators so the loads overlap.
+// Sum of the slots q0, q0 + step, ... below q1 of one partial column
+// (stride `slot` floats), four independent FP64 accumulators so the loads
+// overlap.
 __device__ __forceinline__ double slot_sum(const float *__restrict__ p, size_t slot,
-                                           int q0, int q1) {
+                                           int q0, int q1, int step) {
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     int q = q0;
-    for (; q + 4 <= q1; q += 4) {
+    for (; q + 3 * step < q1; q += 4 * step) {
         a0 += (double)p[(size_t)q * slot];
-        a1 += (double)p[(size_t)(q + 1) * slot];
-        a2 += (double)p[(size_t)(q + 2) * slot];
-        a3 += (double)p[(size_t)(q + 3) * slot];
+        a1 += (double)p[(size_t)(q + step) * slot];
+        a2 += (double)p[(size_t)(q + 2 * step) * slot];
+        a3 += (double)p[(size_t)(q + 3 * step) * slot];
     }
-    for (; q < q1; ++q) a0 += (double)p[(size_t)q * slot];
+    for (; q < q1; q += step) a0 += (double)p[(size_t)q * slot];
     return (a0 + a1) + (a2 + a3);
 }
 
-// One thread per (row j, component k) of one instance.
+// FIN_SLICES threads per (row j, component k): slice s sums the slots
+// congruent to s mod FIN_SLICES; slice 0 adds the slices in order and does
+// the FP64 combine.
+constexpr int FIN_SLICES = 2;
 template <int MM>
-__global__ __launch_bounds__(FIN_ROWS) void finalize_kernel(
+__global__ __launch_bounds__(FIN_ROWS *FIN_SLICES) void finalize_kernel(
     const InstDesc *__restrict__ insts, const RowItem *__restrict__ rows, int cur,
     int want_com) {
-    __shared__ double sh[FIN_ROWS / WAVE];
+    __shared__ double part[FIN_SLICES][FIN_ROWS];
+    __shared__ double sh[FIN_ROWS * FIN_SLICES / WAVE];
     const RowItem ri = rows[blockIdx.x];
     const InstDesc &b = insts[ri.inst];
     if (b.st->done) return;
@@ -418,23 +423,39 @@ __global__ __launch_bounds__(FIN_ROWS) void finalize_kernel(
     const double *__restrict__ Winv = b.Winv;
     const double *__restrict__ wmat = b.wmat;
     float *__restrict__ Xout = b.Xs[cur ^ 1];
-    const int j = ri.bx * FIN_ROWS + threadIdx.x;
-    double com = 0.0;
+    const int r = threadIdx.x % FIN_ROWS, sl = threadIdx.x / FIN_ROWS;
+    const int j = ri.bx * FIN_ROWS + r;
+    // tiles holding j as a row: (I, J) for J in [jlo, ntc);
+    // as a column: (I, Jc) for I in [0, ihi).
+    // (closed forms of the first J and the count of I with tile_exists)
+    int jlo = ntc, ihi = 0;
     if (j < g.n) {
-        // tiles holding j as a row: (I, J) for J in [jlo, ntc);
-        // as a column: (I, Jc) for I in [0, ihi).
         const int I = j / g.th, Jc = j / g.tw;
-        int jlo = (I * g.th) / g.tw;
-        while (jlo < ntc && !tile_exists(g, I, jlo)) ++jlo;
-        int ihi = 0;
-        while (ihi < g.ntr && tile_exists(g, ihi, Jc)) ++ihi;
-        const size_t slot = (size_t)D * npad;
-        double bx[MM];
-        for (int q = 0; q < m; ++q) {
+        jlo = min((I * g.th + 1) / g.tw, ntc);
+        if (jlo < ntc && !tile_exists(g, I, jlo)) jlo = ntc;
+        const int cmax = min((Jc + 1) * g.tw, g.n) - 1;
+        ihi = cmax < 1 ? 0 : min(g.ntr, (cmax - 1) / g.th + 1);
+    }
+    const size_t slot = (size_t)D * npad;
+    double bx[MM];
+    for (int q = 0; q < m; ++q) {
+        double sq = 0.0;
+        if (j < g.n) {
             const float *Pb = P + (size_t)q * S * slot + (size_t)k * npad + j;
-            const double s = slot_sum(Pb, slot, ntc, ntc + ihi) - slot_sum(Pb, slot, jlo, ntc);
-            bx[q] = wmat[q * m + q] * s;
+            sq = slot_sum(Pb, slot, ntc + sl, ntc + ihi, FIN_SLICES) -
+                 slot_sum(Pb, slot, jlo + sl, ntc, FIN_SLICES);
         }
+        part[sl][r] = sq;
+        __syncthreads();
+        if (sl == 0) {
+            double t = part[0][r];
+            for (int e = 1; e < FIN_SLICES; ++e) t += part[e][r];
+            bx[q] = wmat[q * m + q] * t;
+        }
+        __syncthreads();
+    }
+    double com = 0.0;
+    if (sl == 0 && j < g.n) {
         float xn[MM];
         const double alpha = b.alpha;
         const float *__restrict__ Xin = b.Xs[cur];
@@ -455,7 +476,7 @@ __global__ __launch_bounds__(FIN_ROWS) void finalize_kernel(
                     const double t = (double)xn[a] - (double)xn[q];
                     com += wmat[a * m + q] * t * t;
                 }
-    } else if (j < npad) {
+    } else if (sl == 0 && j < npad) {
         for (int a = 0; a < m; ++a) Xout[((size_t)a * D + k) * npad + j] = 0.f;
     }
     if (want_com) {
@@ -649,7 +670,7 @@ hipError_t launch_stream(int D, int variant, int vec4, const InstDesc *insts,
 hipError_t launch_finalize(int maxm, const InstDesc *insts, const RowItem *rows, int nrows,
                            int cur, bool want_com, hipStream_t s) {
     if (nrows == 0) return hipSuccess;
-    const dim3 grid((unsigned)nrows), block(FIN_ROWS);
+    const dim3 grid((unsigned)nrows), block(FIN_ROWS * FIN_SLICES);
     if (maxm <= 4)
         finalize_kernel<4><<<grid, block, 0, s>>>(insts, rows, cur, want_com);
     else if (maxm <= 8)
