@@ -42,10 +42,10 @@ __device__ __forceinline__ float gelu_grad(float z) {
 // instruction: lane l supplies A[l % 16][8 (l / 16) + e] and
 // B[8 (l / 16) + e][l % 16], e = 0..7 (16 contiguous bytes of a k-row), and
 // receives C[4 (l / 16) + v][l % 16], v = 0..3.  Fragments are loaded
-// straight from global memory (L2-resident at these sizes), the next K step
-// while the current one is multiplied.
+// straight from global memory (L2-resident at these sizes), three K steps
+// ahead of the one being multiplied.
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-constexpr int GB = 64, GK = 32;
+constexpr int GB = 64, GK = 32, GNB = 4;
 
 union Frag {
     uint4 u;
@@ -82,32 +82,35 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K,
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-    bf8 a[2], b[2], an[2], bn[2];
+    // ring of GNB register stages: the loads of K step s + GNB - 1 are issued
+    // before step s is multiplied
+    bf8 a[GNB][2], b[GNB][2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        a[i] = load_frag<VEC>(A, lda, m0 + 16 * i + li, M, lk, K);
-        b[i] = load_frag<VEC>(Bt, ldb, n0 + 16 * i + li, N, lk, K);
-    }
-    for (int k0 = 0; k0 < K; k0 += GK) {
-        const bool more = k0 + GK < K;
-        if (more) {
+    for (int st = 0; st < GNB - 1; ++st)
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                an[i] = load_frag<VEC>(A, lda, m0 + 16 * i + li, M, k0 + GK + lk, K);
-                bn[i] = load_frag<VEC>(Bt, ldb, n0 + 16 * i + li, N, k0 + GK + lk, K);
-            }
+        for (int i = 0; i < 2; ++i) {
+            a[st][i] = load_frag<VEC>(A, lda, m0 + 16 * i + li, M, st * GK + lk, K);
+            b[st][i] = load_frag<VEC>(Bt, ldb, n0 + 16 * i + li, N, st * GK + lk, K);
         }
+    for (int k0 = 0; k0 < K; k0 += GNB * GK) {
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int u = 0; u < GNB; ++u) {
+            const int kk = k0 + u * GK;
+            if (kk >= K) break;
+            const int kn = kk + (GNB - 1) * GK, un = (u + GNB - 1) % GNB;
+            if (kn < K) {
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-        if (more) {
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                a[i] = an[i];
-                b[i] = bn[i];
+                for (int i = 0; i < 2; ++i) {
+                    a[un][i] = load_frag<VEC>(A, lda, m0 + 16 * i + li, M, kn + lk, K);
+                    b[un][i] = load_frag<VEC>(Bt, ldb, n0 + 16 * i + li, N, kn + lk, K);
+                }
             }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u][i], b[u][j], acc[i][j],
+                                                                        0, 0, 0);
         }
     }
 #pragma unroll
