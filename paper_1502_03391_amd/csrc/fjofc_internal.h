@@ -29,31 +29,44 @@ struct EmbedState {
 };
 
 // Geometry of the tiled strict-upper-triangle stream of one n x n block.
-// Tiles are th rows x tw columns (tw = 64 lanes x cpl columns per lane);
-// tile (I, J) covers rows [I th, I th + th) and columns [J tw, J tw + tw)
-// and exists when it holds at least one pair j < l inside n.
+// Tiles are th rows x tw columns (tw = 64 lanes x cpl columns per lane).
+// The tiling is staggered along the diagonal: row block I covers rows
+// [I th, I th + th) and its tiles J = 0, 1, ... cover columns
+// [c0, c0 + tw) with c0 = I th + J tw, so each row block's first tile
+// starts on the diagonal (a diagonal tile wastes th^2 / 2 pairs instead of
+// up to th tw / 2).  Tile (I, J) exists when it holds a pair j < l inside n.
 struct TriGeom {
     int n;          // objects
     int m;          // modalities
-    int npad;       // row pitch of SoA buffers (multiple of th and tw)
+    int npad;       // row pitch of SoA buffers (>= n + tw; multiple of th and tw)
     int th, tw;     // tile height and width
     int cpl;        // columns per lane (4 or 8)
     int variant;    // stream-kernel variant: (cpl, rows per group, buffering)
-    int ntr, ntc;   // row / column blocks
+    int ntr, ntc;   // row blocks / most tiles in a row block (that of block 0)
     int nint;       // interior tiles per modality (no masking needed)
     int nbnd;       // boundary tiles per modality (diagonal or ragged)
     int vec4;       // 1: rows are 16-byte aligned (n % 4 == 0)
 };
 
+__host__ __device__ inline int tile_col0(const TriGeom &g, int I, int J) {
+    return I * g.th + J * g.tw;
+}
+
 __host__ __device__ inline bool tile_exists(const TriGeom &g, int I, int J) {
-    const int cmax = min((J + 1) * g.tw, g.n) - 1;
-    return cmax > I * g.th;
+    const int c0 = tile_col0(g, I, J);
+    return c0 < g.n && min(c0 + g.tw, g.n) - 1 > I * g.th;
+}
+
+// Tiles in row block I: ceil((n - I th) / tw).
+__host__ __device__ inline int row_tiles(const TriGeom &g, int I) {
+    const int rem = g.n - I * g.th;
+    return rem > 0 ? (rem + g.tw - 1) / g.tw : 0;
 }
 
 // Partial sums produced by the stream, FP32, layout [m][S][D][npad] with
 // S = ntc + ntr slots: slot J holds row sums of tile (I, J) for the rows of
-// block I, slot ntc + I holds column sums of tile (I, J) for the columns of
-// block J.
+// block I, slot ntc + I holds column sums of tile (I, J) for its columns
+// (the tiles of one row block cover disjoint columns).
 inline size_t partial_floats(const TriGeom &g, int D) {
     return (size_t)g.m * (g.ntc + g.ntr) * D * g.npad;
 }

@@ -199,8 +199,11 @@ int check_weights(int m, const double *wmat) {
 // Tile lists of the strict upper triangle: interior tiles (entirely above
 // the diagonal and inside n) first, then boundary tiles (crossing the
 // diagonal or the ragged edge), each in row-major order.
+// No masking needed: every row below n, every column below n, and every
+// row below every column.
 bool tile_interior(const TriGeom &g, int I, int J) {
-    return (I + 1) * g.th <= g.n && (J + 1) * g.tw <= g.n && J * g.tw >= (I + 1) * g.th;
+    const int c0 = tile_col0(g, I, J);
+    return (I + 1) * g.th <= g.n && c0 + g.tw <= g.n && c0 >= (I + 1) * g.th;
 }
 
 // Stream-kernel variants: columns per lane, rows reduced per group, and
@@ -314,8 +317,9 @@ int plan_instance(const float *const *delta, int m, int n, const double *wmat, i
     choose_tiles(n, d, g.th, g.variant);
     g.cpl = kVariants[g.variant].cpl;
     g.tw = WAVE * g.cpl;
+    // staggered tiles reach up to column n - 1 + tw
     const int unit = std::max(g.th, g.tw);
-    g.npad = (n + unit - 1) / unit * unit;
+    g.npad = (n + g.tw + unit - 1) / unit * unit;
     g.ntr = (n + g.th - 1) / g.th;
     g.ntc = (n + g.tw - 1) / g.tw;
     bool al = (n % 4) == 0;

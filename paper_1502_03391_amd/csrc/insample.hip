@@ -269,7 +269,7 @@ __device__ __forceinline__ void stream_tile(
     const int S = g.ntc + g.ntr;
     const float *__restrict__ dl = dp.p[i];
     const float *__restrict__ X = Xs + (size_t)i * D * npad;
-    const int c0 = J * g.tw, r0 = I * g.th;
+    const int c0 = tile_col0(g, I, J), r0 = I * g.th;
     const int nr = MASK ? min(g.th, n - r0) : g.th;
 
     float xc[CPL][D];
@@ -425,16 +425,16 @@ __global__ __launch_bounds__(FIN_ROWS *FIN_SLICES) void finalize_kernel(
     float *__restrict__ Xout = b.Xs[cur ^ 1];
     const int r = threadIdx.x % FIN_ROWS, sl = threadIdx.x / FIN_ROWS;
     const int j = ri.bx * FIN_ROWS + r;
-    // tiles holding j as a row: (I, J) for J in [jlo, ntc);
-    // as a column: (I, Jc) for I in [0, ihi).
-    // (closed forms of the first J and the count of I with tile_exists)
-    int jlo = ntc, ihi = 0;
+    // tiles holding j as a row: (I, J) for J in [0, row_tiles(I)); as a
+    // column: one tile of every row block I' <= j / th (the tiles of a row
+    // block start on its diagonal and cover the columns after it).
+    // A row block whose only row is n - 1 holds no pair and has no tiles.
+    int jhi = 0, ihi = 0;
     if (j < g.n) {
-        const int I = j / g.th, Jc = j / g.tw;
-        jlo = min((I * g.th + 1) / g.tw, ntc);
-        if (jlo < ntc && !tile_exists(g, I, jlo)) jlo = ntc;
-        const int cmax = min((Jc + 1) * g.tw, g.n) - 1;
-        ihi = cmax < 1 ? 0 : min(g.ntr, (cmax - 1) / g.th + 1);
+        const int I = j / g.th;
+        const bool live = g.n - 1 > I * g.th;
+        jhi = live ? row_tiles(g, I) : 0;
+        ihi = I + (live ? 1 : 0);
     }
     const size_t slot = (size_t)D * npad;
     double bx[MM];
@@ -443,7 +443,7 @@ __global__ __launch_bounds__(FIN_ROWS *FIN_SLICES) void finalize_kernel(
         if (j < g.n) {
             const float *Pb = P + (size_t)q * S * slot + (size_t)k * npad + j;
             sq = slot_sum(Pb, slot, ntc + sl, ntc + ihi, FIN_SLICES) -
-                 slot_sum(Pb, slot, jlo + sl, ntc, FIN_SLICES);
+                 slot_sum(Pb, slot, sl, jhi, FIN_SLICES);
         }
         part[sl][r] = sq;
         __syncthreads();
