@@ -71,7 +71,7 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs the whole hot path on a "
+        print("bench.py measures one GPU: the library runs the whole hot path on a "
               "single MI355X; --gpus above 1 is not supported.", file=sys.stderr)
         sys.exit(2)
     import numpy as np

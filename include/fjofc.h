@@ -244,7 +244,8 @@ int fjofc_embed_batched(fjofc_ctx *ctx, const fjofc_problem *probs, int count,
  * Learned warm start for out-of-sample embedding: a multilayer perceptron
  * mapping a new object's dissimilarities to a fixed set of in-sample
  * landmark objects (all modalities) to a starting point for the Section 3
- * iteration, refined there by Guttman transforms (which also judge it).
+ * iteration, refined there by Guttman transforms (which also measure its
+ * error).
  * Layers l = 0..L-1: z = h W_l + b_l (W_l is dims[l] x dims[l+1],
  * row-major), h' = GELU(z) = z Phi(z) after every layer but the last.
  * Products run on BF16 matrix cores with FP32 accumulation: FP32 master
