@@ -41,7 +41,7 @@ def _gpu_init(ctx, delta, d, iters):
 
 
 @pytest.mark.parametrize("m,n,d,lat", [(3, 400, 3, 4), (2, 257, 5, 8), (2, 120, 8, 8),
-                                       (1, 64, 2, 3)])
+                                       (1, 64, 2, 3), (2, 6, 2, 3)])
 def test_init_matches_dense_oracle(ctx, m, n, d, lat):
     views, _, _ = gen.latent_views(80 + n, n, m, lat, 0.2, d)
     delta = [gen.pairwise_dist_np(Y).astype(np.float32) for Y in views]
