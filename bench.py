@@ -62,9 +62,9 @@ def parse():
     ap.add_argument("--iters", type=int, default=None,
                     help="transforms per step (default: the workload's 300); "
                          "for short profiled runs only")
-    ap.add_argument("--extras", default="relaxed,init,oos,batched,warmstart",
+    ap.add_argument("--extras", default="relaxed,init,paper,early,oos,batched,warmstart",
                     help="comma list of extra workloads to measure after the main one "
-                         "(relaxed, init, oos, batched, warmstart) or 'none'")
+                         "(relaxed, init, paper, early, oos, batched, warmstart) or 'none'")
     return ap.parse_args()
 
 
@@ -169,6 +169,10 @@ def main():
         out["extra"]["init"] = bench_init(ctx, delta, wmat, res["stress"], iters, every)
     del delta, X, X0d
     torch.cuda.empty_cache()
+    if "paper" in extras:
+        out["extra"]["paper"] = bench_paper_shape(ctx)
+    if "early" in extras:
+        out["extra"]["early_stop"] = bench_early_stop(ctx)
     if "oos" in extras:
         out["extra"]["oos"] = bench_oos(ctx)
     if "batched" in extras:
@@ -301,6 +305,110 @@ def bench_init(ctx, delta, wmat, random_final, iters, every, init_iters=20):
     print(f"[bench] paper start: init {t_init:.3f} s, {r['iters_run']} transforms "
           f"({t_embed:.3f} s) to the random start's {iters}-transform stress",
           file=sys.stderr, flush=True)
+    return out
+
+
+def bench_paper_shape(ctx, reps=5):
+    """The paper's matched-setting shape (n = 400, m = 3, d = 2) run to its
+    stop rule (normalised stress decreasing by less than 1e-6) from its own
+    start (cMDS + Procrustes), on the paper's matched-setting recipe (jittered
+    copies of a 2-D Gaussian sample); w = 0.5, which the paper does not state.
+    The paper's own figure for this setting is quoted as context, with its
+    hardware."""
+    import numpy as np
+    import torch
+    from paper_1502_03391_amd import fjofc
+    from workloads import generators as gen
+    n, m, d = 400, 3, 2
+    dev = torch.device("cuda:0")
+    views = gen.matched_views(400, n, m)
+    delta = [gen.pairwise_dist_torch(Y, dev) for Y in views]
+    wmat = gen.uniform_wmat(m, 0.5)
+    X = torch.empty((m * n, d), device=dev)
+    times, res = [], None
+    for _ in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fjofc.fjofc_init_cmds(ctx, delta, X, iters=20)
+        res, _ = fjofc.fjofc_embed(ctx, delta, wmat, X, 5000, tol=1e-6,
+                                   tol_mode=fjofc.FJOFC_TOL_PAPER, stress_every=1)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    sec = float(np.median(times[1:]))
+    return {"workload": "paper_matched_n400_m3_d2", "seconds_to_stop": sec,
+            "transforms": res["iters_run"], "converged": bool(res["converged"]),
+            "final_stress_norm": res["stress_norm"],
+            "paper_context": {"seconds": 1.39, "final_stress_norm": 0.03,
+                              "hardware": "2.6 GHz Intel Core i5, serial",
+                              "data": "same recipe, the paper's own draws"}}
+
+
+def bench_early_stop(ctx, reps=25, ks=(1, 2, 5, 10, 25, 50, 100, 200)):
+    """The error-tolerance experiment of Section 4.2: for the matched and the
+    anomaly setting (10 anomalous rows in the last view) with m = 4, 5, 6,
+    n = 400, d = 2, w = 0.5, each draw starts at the paper's start and records
+    ||X_final - X_k||_F / ||X_final||_F at the listed k (over non-anomalous
+    rows only in the anomaly setting) for two X_final: the paper's stop rule
+    (normalised stress decreasing by less than 1e-6) and a tight one (relative
+    decrease below 1e-10, at most 5000 transforms).  Reports the means and
+    2 s.e. over the draws, and the mean transforms to each stop."""
+    import numpy as np
+    import torch
+    from paper_1502_03391_amd import fjofc
+    from workloads import generators as gen
+    n, d, n_anom = 400, 2, 10
+    dev = torch.device("cuda:0")
+    t_start = time.perf_counter()
+    out = {"workload": "paper_error_tolerance_n400_d2", "reps": reps, "k": list(ks),
+           "norm": "Frobenius", "paper_context": "about 5% relative error at k = 25 in the "
+           "anomaly setting, which needs over 100 transforms on average to stop"}
+    for setting in ("matched", "anomaly"):
+        for m in (4, 5, 6):
+            wmat = gen.uniform_wmat(m, 0.5)
+            keep = torch.ones(m * n, dtype=torch.bool, device=dev)
+            if setting == "anomaly":
+                keep[(m - 1) * n:(m - 1) * n + n_anom] = False
+            errs = {"paper": [], "tight": []}
+            stops = {"paper": [], "tight": []}
+            for r in range(reps):
+                views = gen.matched_views(1000 * m + r, n, m,
+                                          n_anom if setting == "anomaly" else 0)
+                delta = [gen.pairwise_dist_torch(Y, dev) for Y in views]
+                X0 = torch.empty((m * n, d), device=dev)
+                fjofc.fjofc_init_cmds(ctx, delta, X0, iters=20)
+                finals = {}
+                for name, tol, mode in (("paper", 1e-6, fjofc.FJOFC_TOL_PAPER),
+                                        ("tight", 1e-10, fjofc.FJOFC_TOL_REL)):
+                    Xf = X0.clone()
+                    res, _ = fjofc.fjofc_embed(ctx, delta, wmat, Xf, 5000, tol=tol,
+                                               tol_mode=mode, stress_every=1)
+                    stops[name].append(res["iters_run"])
+                    finals[name] = Xf[keep].double()
+                Xk, done = X0.clone(), 0
+                rows = {"paper": [], "tight": []}
+                for k in ks:
+                    fjofc.fjofc_embed(ctx, delta, wmat, Xk, k - done,
+                                      tol_mode=fjofc.FJOFC_TOL_NONE, stress_every=k - done)
+                    done = k
+                    for name, ref in finals.items():
+                        rows[name].append(float((ref - Xk[keep].double()).norm() / ref.norm()))
+                for name in rows:
+                    errs[name].append(rows[name])
+            cell = {}
+            for name in ("paper", "tight"):
+                e = np.asarray(errs[name])
+                se = e.std(axis=0, ddof=1) / np.sqrt(reps)
+                cell[name] = {"rel_err_mean": e.mean(axis=0).tolist(),
+                              "rel_err_2se": (2 * se).tolist(),
+                              "transforms_to_stop_mean": float(np.mean(stops[name]))}
+            out[f"{setting}_m{m}"] = cell
+    out["seconds"] = time.perf_counter() - t_start
+    a = out["anomaly_m4"]
+    print(f"[bench] error tolerance: anomaly m=4: paper stop after "
+          f"{a['paper']['transforms_to_stop_mean']:.0f} transforms, tight after "
+          f"{a['tight']['transforms_to_stop_mean']:.0f}; err@25 vs tight "
+          f"{a['tight']['rel_err_mean'][list(ks).index(25)]:.4f} "
+          f"({out['seconds']:.1f} s)", file=sys.stderr, flush=True)
     return out
 
 

@@ -55,6 +55,27 @@ def latent_views(seed: int, n: int, m: int, lat: int, sigma: float,
     return views, maps, X0
 
 
+def matched_views(seed: int, n: int = 400, m: int = 3, anomalies: int = 0):
+    """The paper's matched setting (Section 4.1): Y has n rows drawn from a
+    2-D Gaussian with mean (5, 5) and identity covariance, z is the range of
+    all of Y's entries, and view i is Y plus independent Uniform(-z/50, z/50)
+    jitter.  With anomalies > 0, the last view is built instead from a copy of
+    Y whose first `anomalies` rows are redrawn from a Gaussian with mean
+    (8, 8) and covariance 2 I (the anomaly setting).  Returns the m views
+    (FP64, n x 2)."""
+    rng = np.random.default_rng(seed)
+    Y = rng.standard_normal((n, 2)) + 5.0
+    z = float(Y.max() - Y.min())
+    views = []
+    for i in range(m):
+        base = Y
+        if anomalies and i == m - 1:
+            base = Y.copy()
+            base[:anomalies] = 8.0 + math.sqrt(2.0) * rng.standard_normal((anomalies, 2))
+        views.append(base + rng.uniform(-z / 50.0, z / 50.0, size=(n, 2)))
+    return views
+
+
 def oos_objects(seed: int, k: int, maps: Sequence[np.ndarray], sigma: float):
     """New objects from the same latent model: k fresh latent points, viewed
     through the in-sample maps with fresh noise.  Returns a list of k x lat
