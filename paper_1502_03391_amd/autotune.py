@@ -22,7 +22,7 @@ TABLE = os.path.join(HERE, "tune_gfx950.txt")
 
 # variant numbers as in the library: 0 = (4 cols/lane, 8-row groups,
 # double-buffered), 1 = (4, 8, single), 2 = (8, 4, single), 3 = (8, 8, single)
-CANDIDATES = [(64, 1), (128, 1), (256, 1), (128, 0), (256, 0),
+CANDIDATES = [(64, 1), (96, 1), (128, 1), (160, 1), (192, 1), (256, 1), (128, 0), (256, 0),
               (64, 2), (128, 2), (256, 2), (128, 3), (256, 3), (512, 3)]
 BUCKETS = [128, 256, 512, 1024, 2048, 4096, 8192, 16384, 1 << 30]
 

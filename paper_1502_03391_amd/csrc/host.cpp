@@ -224,6 +224,9 @@ struct TuneRow {
     int d, nmax, th, variant;
 };
 
+// A tile height is a multiple of the 8-row group of every variant.
+bool valid_th(int th) { return th >= 8 && th <= 2048 && th % 8 == 0; }
+
 std::vector<TuneRow> &tune_table() {
     static std::vector<TuneRow> rows;
     static bool loaded = false;
@@ -247,8 +250,7 @@ std::vector<TuneRow> &tune_table() {
             TuneRow r;
             if (line[0] == '#') continue;
             if (std::sscanf(line, "%d %d %d %d", &r.d, &r.nmax, &r.th, &r.variant) == 4 &&
-                r.variant >= 0 && r.variant < kNumVariants && r.th >= 8 && r.th <= 2048 &&
-                (r.th & (r.th - 1)) == 0)
+                r.variant >= 0 && r.variant < kNumVariants && valid_th(r.th))
                 rows.push_back(r);
         }
         std::fclose(f);
@@ -268,8 +270,7 @@ void choose_tiles(int n, int d, int &th, int &variant) {
         }
     if (const char *e = std::getenv("FJOFC_TILE")) {
         int a = 0, b = 0;
-        if (std::sscanf(e, "%d:%d", &a, &b) == 2 && b >= 0 && b < kNumVariants && a >= 8 &&
-            a <= 2048 && (a & (a - 1)) == 0) {
+        if (std::sscanf(e, "%d:%d", &a, &b) == 2 && b >= 0 && b < kNumVariants && valid_th(a)) {
             th = a;
             variant = b;
         }
@@ -378,17 +379,24 @@ InstDesc make_desc(char *base, const HostInst &h, const size_t offs[9], EmbedSta
     return d;
 }
 
-// Work items of one instance: interior tiles of every modality first, then
-// the boundary tiles (half-empty diagonal tiles dispatched last shorten the
-// tail of the launch).  `bnd` receives the boundary items when given, so a
-// batch can put all its boundary items after all interior ones.
+// Work items of one instance.  A boundary tile evaluates every pair of its
+// th x tw block plus the masks, so it costs more than an interior tile; on
+// its own an instance dispatches its boundary tiles first and lets the
+// uniform interior tiles fill the tail of the launch (measured 1.5-4%
+// shorter launches at n = 20000).  `bnd` receives the boundary items when
+// given: a batch collects them from all its instances and appends them
+// after all interior items (the order made no measurable difference there).
 void append_items(int inst, const HostInst &h, std::vector<StreamItem> &items,
                   std::vector<StreamItem> *bnd = nullptr) {
-    std::vector<StreamItem> &b = bnd ? *bnd : items;
+    auto boundary = [&](std::vector<StreamItem> &out) {
+        for (int i = 0; i < h.g.m; ++i)
+            for (int t = h.g.nint; t < (int)h.tiles.size(); ++t)
+                out.push_back({inst, i, h.tiles[t], t});
+    };
+    if (!bnd) boundary(items);
     for (int i = 0; i < h.g.m; ++i)
         for (int t = 0; t < h.g.nint; ++t) items.push_back({inst, i, h.tiles[t], t});
-    for (int i = 0; i < h.g.m; ++i)
-        for (int t = h.g.nint; t < (int)h.tiles.size(); ++t) b.push_back({inst, i, h.tiles[t], t});
+    if (bnd) boundary(*bnd);
 }
 
 void append_rows(int inst, const HostInst &h, std::vector<RowItem> &rows) {

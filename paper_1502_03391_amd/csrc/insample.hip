@@ -351,7 +351,7 @@ __device__ __forceinline__ void stream_tile(
 
 // Stream kernel: one wavefront per work item.  Items of interior tiles run
 // the unmasked instance, boundary tiles (crossing the diagonal or the
-// ragged edge; listed after the interior ones) the masked instance.
+// ragged edge) the masked instance.
 template <int D, int CPL, int G, bool DBUF, bool VEC4, bool STRESS, bool ACC>
 __global__ __launch_bounds__(WAVE) void bx_kernel(
     const InstDesc *__restrict__ insts, const StreamItem *__restrict__ items, int cur) {

@@ -82,14 +82,16 @@ def test_config0_parity(ctx):
     assert np.all(np.diff(hg[ok]) <= 1e-6 * hg[ok][:-1])
 
 
-@pytest.mark.parametrize("tile", ["256:0", "128:1", "64:2", "512:3", "512:1", "32:1", "16:2"])
+@pytest.mark.parametrize("tile", ["256:0", "128:1", "64:2", "512:3", "512:1", "32:1", "16:2",
+                                  "24:1", "96:3", "160:0", "200:2"])
 @pytest.mark.parametrize("m,n,d", [(1, 2, 1), (2, 3, 2), (3, 7, 3), (2, 64, 5),
                                    (2, 255, 2), (3, 256, 5), (2, 257, 3),
                                    (4, 300, 8), (2, 513, 4), (3, 1000, 5),
                                    (2, 1030, 6), (2, 777, 7)])
 def test_one_transform_parity(ctx, monkeypatch, tile, m, n, d):
-    """One Guttman transform and the stress of X0 and X1, across tile shapes,
-    ragged tails (n not a multiple of the tile or of 4) and all d."""
+    """One Guttman transform and the stress of X0 and X1, across tile shapes
+    (heights that are powers of two or only multiples of 8), ragged tails (n
+    not a multiple of the tile or of 4) and all d."""
     monkeypatch.setenv("FJOFC_TILE", tile)
     wmat = _general_wmat(m, seed=n)
     delta, _, X0 = _problem(100 + n + d, m, n, d, wmat=wmat)
