@@ -21,9 +21,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(HERE, "tune_gfx950.txt")
 
 # variant numbers as in the library: 0 = (4 cols/lane, 8-row groups,
-# double-buffered), 1 = (4, 8, single), 2 = (8, 4, single), 3 = (8, 8, single)
+# double-buffered), 1 = (4, 8, single), 2 = (8, 4, single), 3 = (8, 8, single);
+# 4 and 5 are variant 1 with 4 x 1 and 2 x 2 wavefronts sharing a tile
 CANDIDATES = [(64, 1), (96, 1), (128, 1), (160, 1), (192, 1), (256, 1), (128, 0), (256, 0),
-              (64, 2), (128, 2), (256, 2), (128, 3), (256, 3), (512, 3)]
+              (64, 2), (128, 2), (256, 2), (128, 3), (256, 3), (512, 3),
+              (256, 4), (384, 4), (512, 4), (128, 5), (256, 5), (384, 5)]
 BUCKETS = [128, 256, 512, 1024, 2048, 4096, 8192, 16384, 1 << 30]
 
 

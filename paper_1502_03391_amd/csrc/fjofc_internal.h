@@ -29,7 +29,8 @@ struct EmbedState {
 };
 
 // Geometry of the tiled strict-upper-triangle stream of one n x n block.
-// Tiles are th rows x tw columns (tw = 64 lanes x cpl columns per lane).
+// Tiles are th rows x tw columns (tw = 64 lanes x cpl columns per lane x
+// the variant's column wavefronts).
 // The tiling is staggered along the diagonal: row block I covers rows
 // [I th, I th + th) and its tiles J = 0, 1, ... cover columns
 // [c0, c0 + tw) with c0 = I th + J tw, so each row block's first tile
@@ -38,10 +39,11 @@ struct EmbedState {
 struct TriGeom {
     int n;          // objects
     int m;          // modalities
-    int npad;       // row pitch of SoA buffers (>= n + tw; multiple of th and tw)
+    int npad;       // row pitch of SoA buffers (>= n + tw; multiple of max(th, tw))
     int th, tw;     // tile height and width
     int cpl;        // columns per lane (4 or 8)
-    int variant;    // stream-kernel variant: (cpl, rows per group, buffering)
+    int variant;    // stream-kernel variant: (cpl, rows per group, buffering,
+                    // wavefronts per tile)
     int ntr, ntc;   // row blocks / most tiles in a row block (that of block 0)
     int nint;       // interior tiles per modality (no masking needed)
     int nbnd;       // boundary tiles per modality (diagonal or ragged)
@@ -102,9 +104,12 @@ struct RowItem {
     int inst, bx, k, pad;
 };
 
+// The finalize and commensurability kernels cover rows [0, npad / FIN_ROWS
+// * FIN_ROWS), which holds every row below n because npad >= n + tw and
+// tw >= FIN_ROWS; each writes one commensurability partial per block.
 constexpr int FIN_ROWS = 256;
 inline int commens_blocks(const TriGeom &g, int D) {
-    return (g.npad + FIN_ROWS - 1) / FIN_ROWS * D;
+    return g.npad / FIN_ROWS * D;
 }
 
 // ---- launchers (insample.hip) ----------------------------------------
@@ -112,7 +117,7 @@ inline int commens_blocks(const TriGeom &g, int D) {
 // the configuration buffer Xs[cur].
 hipError_t launch_stream(int D, int variant, int vec4, const InstDesc *insts,
                          const StreamItem *items, int nitems, int cur,
-                         bool stress, bool acc, hipStream_t s);
+                         bool stress, bool acc, size_t lds, hipStream_t s);
 hipError_t launch_finalize(int maxm, const InstDesc *insts, const RowItem *rows,
                            int nrows, int cur, bool want_com, hipStream_t s);
 hipError_t launch_com(const InstDesc *insts, const RowItem *rows, int nrows,

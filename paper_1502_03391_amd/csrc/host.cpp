@@ -206,13 +206,15 @@ bool tile_interior(const TriGeom &g, int I, int J) {
     return (I + 1) * g.th <= g.n && c0 + g.tw <= g.n && c0 >= (I + 1) * g.th;
 }
 
-// Stream-kernel variants: columns per lane, rows reduced per group, and
-// whether the row loads are double-buffered.  Numbering shared with the
-// kernels' dispatch.
+// Stream-kernel variants: columns per lane, rows reduced per group,
+// whether the row loads are double-buffered, and the R x C wavefronts that
+// share one tile (each takes th / R rows and 64 cpl columns, so tw =
+// 64 cpl C).  Numbering shared with the kernels' dispatch.
 struct Variant {
-    int cpl, g, dbuf;
+    int cpl, g, dbuf, r, c;
 };
-constexpr Variant kVariants[] = {{4, 8, 1}, {4, 8, 0}, {8, 4, 0}, {8, 8, 0}};
+constexpr Variant kVariants[] = {{4, 8, 1, 1, 1}, {4, 8, 0, 1, 1}, {8, 4, 0, 1, 1},
+                                 {8, 8, 0, 1, 1}, {4, 8, 0, 4, 1}, {4, 8, 0, 2, 2}};
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 constexpr int kDefaultVariant = 3;
 
@@ -275,6 +277,18 @@ void choose_tiles(int n, int d, int &th, int &variant) {
             variant = b;
         }
     }
+    // each of the variant's R row slabs holds whole 8-row groups
+    const int unit = 8 * kVariants[variant].r;
+    th = (th + unit - 1) / unit * unit;
+}
+
+// Dynamic LDS of one stream workgroup: the row sums [C][D][th], column sums
+// [R][D][tw] and one double per wavefront (none with a single wavefront).
+size_t stream_lds(const TriGeom &g, int D) {
+    const Variant &v = kVariants[g.variant];
+    if (v.r * v.c == 1) return 0;
+    return ((size_t)v.c * g.th + (size_t)v.r * g.tw) * D * sizeof(float) +
+           (size_t)v.r * v.c * sizeof(double);
 }
 
 int check_problem(const float *const *delta, int m, int n, int d, const void *X) {
@@ -316,11 +330,17 @@ int plan_instance(const float *const *delta, int m, int n, const double *wmat, i
     g.n = n;
     g.m = m;
     choose_tiles(n, d, g.th, g.variant);
-    g.cpl = kVariants[g.variant].cpl;
-    g.tw = WAVE * g.cpl;
-    // staggered tiles reach up to column n - 1 + tw
+    const Variant &var = kVariants[g.variant];
+    g.cpl = var.cpl;
+    g.tw = WAVE * var.cpl * var.c;
+    // the workgroup's partial sums stay within 64 KB of LDS
+    while (stream_lds(g, d) > 65536 && g.th > 8 * var.r) g.th -= 8 * var.r;
+    // staggered tiles reach up to column n - 1 + tw; a multiple of th keeps
+    // every row block's rows below npad
     const int unit = std::max(g.th, g.tw);
     g.npad = (n + g.tw + unit - 1) / unit * unit;
+    if (g.tw < FIN_ROWS || g.npad / FIN_ROWS * FIN_ROWS < n)
+        return fail(FJOFC_EINVAL, "internal: row padding %d does not cover n=%d", g.npad, n);
     g.ntr = (n + g.th - 1) / g.th;
     g.ntc = (n + g.tw - 1) / g.tw;
     bool al = (n % 4) == 0;
@@ -431,6 +451,7 @@ struct StreamGroup {
     const StreamItem *items;
     int nitems;
     double bytes;  // algorithmic bytes of one launch
+    size_t lds;    // dynamic LDS per workgroup (largest over the group's instances)
 };
 
 // Enqueue Algorithm 2's loop for instances advancing in lockstep.  Used
@@ -445,7 +466,7 @@ int enqueue_loop(fjofc_ctx *ctx, const InstDesc *insts, int count, int maxm,
         for (const StreamGroup &gr : groups) {
             Timed tm(ctx, acc ? K_STREAM : K_EDGE, gr.bytes, s);
             HIP_TRY(launch_stream(gr.D, gr.variant, gr.vec4, insts, gr.items, gr.nitems, cur,
-                                  stress, acc, s));
+                                  stress, acc, gr.lds, s));
         }
         return FJOFC_OK;
     };
@@ -520,7 +541,8 @@ int run_insample(fjofc_ctx *ctx, const float *const *delta, int m, int n,
     HIP_TRY(hipMemcpyAsync(const_cast<double *>(desc.wmat), wmat, sizeof(double) * m * m,
                            hipMemcpyHostToDevice, s));
     const double bytes = 4.0 * m * 0.5 * n * (n - 1.0);
-    std::vector<StreamGroup> groups{{d, h.g.variant, h.g.vec4, d_items, (int)items.size(), bytes}};
+    std::vector<StreamGroup> groups{
+        {d, h.g.variant, h.g.vec4, d_items, (int)items.size(), bytes, stream_lds(h.g, d)}};
     rc = enqueue_loop(ctx, d_desc, 1, m, groups, d_rows, (int)rows.size(), iters, tol, tol_mode,
                       stress_every, iters + 1, stress_only, s);
     if (rc) return rc;
@@ -830,6 +852,7 @@ int fjofc_batch_create(fjofc_ctx *ctx, const fjofc_problem *probs, int count,
     }
     std::map<std::tuple<int, int, int>, std::vector<StreamItem>> gitems, gbnd;
     std::map<std::tuple<int, int, int>, double> gbytes;
+    std::map<std::tuple<int, int, int>, size_t> glds;
     std::vector<RowItem> rows;
     // largest problems first within each group: long items start early
     std::vector<int> order(count);
@@ -843,6 +866,7 @@ int fjofc_batch_create(fjofc_ctx *ctx, const fjofc_problem *probs, int count,
         const auto key = std::make_tuple(h.D, h.g.variant, h.g.vec4);
         append_items(p, h, gitems[key], &gbnd[key]);
         gbytes[key] += 4.0 * h.g.m * 0.5 * h.g.n * (h.g.n - 1.0);
+        glds[key] = std::max(glds[key], stream_lds(h.g, h.D));
     }
     for (auto &kv : gitems) kv.second.insert(kv.second.end(), gbnd[kv.first].begin(), gbnd[kv.first].end());
     for (int p = 0; p < count; ++p) append_rows(p, b->hi[p], rows);
@@ -883,7 +907,7 @@ int fjofc_batch_create(fjofc_ctx *ctx, const fjofc_problem *probs, int count,
         StreamItem *d = reinterpret_cast<StreamItem *>(base + o_groups[gi++]);
         copy(d, kv.second.data(), kv.second.size() * sizeof(StreamItem));
         b->groups.push_back({std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
-                             d, (int)kv.second.size(), gbytes[kv.first]});
+                             d, (int)kv.second.size(), gbytes[kv.first], glds[kv.first]});
     }
     b->d_rows = reinterpret_cast<RowItem *>(base + o_rows);
     b->nrows = (int)rows.size();

@@ -186,12 +186,13 @@ __device__ __forceinline__ void load_rows(float (&dv)[G][CPL],
     }
 }
 
-// Terms of G rows (given in dv) against the lane's CPL columns.
+// Terms of G rows (given in dv) against the lane's CPL columns.  The G row
+// sums go to rsink[k * rpitch + rbase + g0 + row].
 template <int D, int CPL, int G, bool VEC4, bool MASK, bool STRESS, bool ACC>
 __device__ __forceinline__ void process_group(
     const float (&dv)[G][CPL], const float *__restrict__ X, int n, int npad,
     int r0, int c0, int g0, int nr, int lane, const float (&xc)[CPL][D],
-    float (&cacc)[CPL][D], float *prow, double &fid) {
+    float (&cacc)[CPL][D], float *rsink, int rpitch, int rbase, double &fid) {
     const int nv = MASK ? min(G, nr - g0) : G;
     // the group's row points (wave-uniform scalar loads; padding rows are 0)
     float xr[G][D];
@@ -252,25 +253,38 @@ __device__ __forceinline__ void process_group(
         if (STRESS) asm volatile("" : "+v"(fs));
         __builtin_amdgcn_sched_barrier(0);
     }
-    if (ACC) reduce_rows_store<D, G>(p, lane, prow, npad, r0 + g0, nv);
+    if (ACC) reduce_rows_store<D, G>(p, lane, rsink, rpitch, rbase + g0, nv);
     if (STRESS) fid += (double)fs;
 }
 
-// One wavefront streams one tile of the strict upper triangle.  MASK is set
-// for boundary tiles: those crossing the diagonal (only l > j counts) or
-// the ragged edge (rows or columns >= n).
-template <int D, int CPL, int G, bool DBUF, bool VEC4, bool MASK, bool STRESS, bool ACC>
+// One workgroup of R x C wavefronts streams one tile of the strict upper
+// triangle: wavefront (wr, wc) takes the tile's rows [wr th/R, (wr+1) th/R)
+// and its columns [wc 64 CPL, (wc+1) 64 CPL).  With one wavefront the row and
+// column sums go straight to the partial buffer.  With several, each
+// wavefront leaves its sums in LDS and, after one barrier, the workgroup adds
+// them in a fixed order (over wc for a row, over wr for a column) and writes
+// each of the tile's rows and columns once, which divides the partial-sum
+// traffic of a th x tw tile by the number of wavefronts sharing a row or
+// column.  MASK is set for boundary tiles: those crossing the diagonal (only
+// l > j counts) or the ragged edge (rows or columns >= n).
+template <int D, int CPL, int G, bool DBUF, bool VEC4, bool MASK, bool STRESS, bool ACC, int R,
+          int C>
 __device__ __forceinline__ void stream_tile(
     const TriGeom &g, const DeltaPtrs &dp, const float *__restrict__ Xs,
     int i, int I, int J, int ftile, float *__restrict__ P,
-    double *__restrict__ F) {
-    const int lane = threadIdx.x;
+    double *__restrict__ F, float *smem) {
+    constexpr int NW = R * C, TWW = WAVE * CPL;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int w = NW == 1 ? 0 : __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int wr = w / C, wc = w - (w / C) * C;
     const int n = g.n, npad = g.npad;
     const int S = g.ntc + g.ntr;
     const float *__restrict__ dl = dp.p[i];
     const float *__restrict__ X = Xs + (size_t)i * D * npad;
-    const int c0 = tile_col0(g, I, J), r0 = I * g.th;
-    const int nr = MASK ? min(g.th, n - r0) : g.th;
+    const int thw = g.th / R;
+    const int ct0 = tile_col0(g, I, J), rt0 = I * g.th;   // the tile
+    const int c0 = ct0 + wc * TWW, r0 = rt0 + wr * thw;   // this wavefront's part
+    const int nr = MASK ? min(thw, n - r0) : thw;
 
     float xc[CPL][D];
 #pragma unroll
@@ -298,6 +312,15 @@ __device__ __forceinline__ void stream_tile(
     double fid = 0.0;
     float *Pm = P + (size_t)i * S * D * npad;
     float *prow = Pm + (size_t)J * D * npad;
+    float *pcol = Pm + (size_t)(g.ntc + I) * D * npad;
+    // LDS layout (several wavefronts): row sums [C][D][th], column sums
+    // [R][D][tw], then one double per wavefront for the fidelity.
+    const int tw = C * TWW;
+    float *srow = smem, *scol = smem + (size_t)C * D * g.th;
+    double *sfid = reinterpret_cast<double *>(scol + (size_t)R * D * tw);
+    float *rsink = NW == 1 ? prow : srow + (size_t)wc * D * g.th;
+    const int rpitch = NW == 1 ? npad : g.th;
+    const int rbase = NW == 1 ? r0 : wr * thw;
 
     if (DBUF) {
         // Two row buffers used alternately (no register copies, so the
@@ -309,13 +332,15 @@ __device__ __forceinline__ void stream_tile(
             if (g0 + G < nr)
                 load_rows<CPL, G, VEC4, MASK>(db, dl, n, r0 + g0 + G, c0, lane, nr - g0 - G);
             process_group<D, CPL, G, VEC4, MASK, STRESS, ACC>(da, X, n, npad, r0, c0, g0, nr,
-                                                              lane, xc, cacc, prow, fid);
+                                                              lane, xc, cacc, rsink, rpitch,
+                                                              rbase, fid);
             if (g0 + G >= nr) break;
             if (g0 + 2 * G < nr)
                 load_rows<CPL, G, VEC4, MASK>(da, dl, n, r0 + g0 + 2 * G, c0, lane,
                                               nr - g0 - 2 * G);
             process_group<D, CPL, G, VEC4, MASK, STRESS, ACC>(db, X, n, npad, r0, c0, g0 + G,
-                                                              nr, lane, xc, cacc, prow, fid);
+                                                              nr, lane, xc, cacc, rsink, rpitch,
+                                                              rbase, fid);
         }
     } else {
         // One row buffer: other wavefronts on the SIMD cover the load latency.
@@ -323,49 +348,87 @@ __device__ __forceinline__ void stream_tile(
             float da[G][CPL];
             load_rows<CPL, G, VEC4, MASK>(da, dl, n, r0 + g0, c0, lane, nr - g0);
             process_group<D, CPL, G, VEC4, MASK, STRESS, ACC>(da, X, n, npad, r0, c0, g0, nr,
-                                                              lane, xc, cacc, prow, fid);
+                                                              lane, xc, cacc, rsink, rpitch,
+                                                              rbase, fid);
         }
     }
     if (ACC) {
-        float *pcol = Pm + (size_t)(g.ntc + I) * D * npad + c0;
+        // this wavefront's column sums: to the partial buffer, or to LDS
+        float *csink = NW == 1 ? pcol + c0 : scol + (size_t)wr * D * tw + wc * TWW;
+        const int cpitch = NW == 1 ? npad : tw;
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             if (VEC4) {
 #pragma unroll
                 for (int h = 0; h < CPL / 4; ++h)
-                    *reinterpret_cast<float4 *>(pcol + (size_t)k * npad + h * 256 + lane * 4) =
+                    *reinterpret_cast<float4 *>(csink + (size_t)k * cpitch + h * 256 + lane * 4) =
                         make_float4(cacc[4 * h][k], cacc[4 * h + 1][k], cacc[4 * h + 2][k],
                                     cacc[4 * h + 3][k]);
             } else {
 #pragma unroll
                 for (int q = 0; q < CPL; ++q)
-                    pcol[(size_t)k * npad + lane_col<false>(lane, q)] = cacc[q][k];
+                    csink[(size_t)k * cpitch + lane_col<false>(lane, q)] = cacc[q][k];
             }
         }
     }
     if (STRESS) {
         fid = wave_sum_d(fid);
-        if (lane == 0) F[(size_t)i * (g.nint + g.nbnd) + ftile] = fid;
+        if (NW == 1) {
+            if (lane == 0) F[(size_t)i * (g.nint + g.nbnd) + ftile] = fid;
+        } else if (lane == 0) {
+            sfid[w] = fid;
+        }
+    }
+    if constexpr (NW > 1) {
+        __syncthreads();
+        if (ACC) {
+            // rows of the tile inside n, each summed over the C wavefronts
+            // that share it
+            const int th = g.th, nrows = MASK ? min(th, n - rt0) : th;
+            for (int q = threadIdx.x; q < D * th; q += NW * WAVE) {
+                const int k = q / th, r = q - k * th;
+                if (r >= nrows) continue;
+                float v = srow[(size_t)k * th + r];
+#pragma unroll
+                for (int c = 1; c < C; ++c) v += srow[((size_t)c * D + k) * th + r];
+                prow[(size_t)k * npad + rt0 + r] = v;
+            }
+            // columns of the tile, each summed over the R wavefronts
+            for (int q = threadIdx.x; q < D * tw; q += NW * WAVE) {
+                const int k = q / tw, c = q - k * tw;
+                float v = scol[(size_t)k * tw + c];
+#pragma unroll
+                for (int rr = 1; rr < R; ++rr) v += scol[((size_t)rr * D + k) * tw + c];
+                pcol[(size_t)k * npad + ct0 + c] = v;
+            }
+        }
+        if (STRESS && threadIdx.x == 0) {
+            double t = sfid[0];
+            for (int q = 1; q < NW; ++q) t += sfid[q];
+            F[(size_t)i * (g.nint + g.nbnd) + ftile] = t;
+        }
     }
 }
 
-// Stream kernel: one wavefront per work item.  Items of interior tiles run
-// the unmasked instance, boundary tiles (crossing the diagonal or the
-// ragged edge) the masked instance.
-template <int D, int CPL, int G, bool DBUF, bool VEC4, bool STRESS, bool ACC>
-__global__ __launch_bounds__(WAVE) void bx_kernel(
+// Stream kernel: one workgroup of R x C wavefronts per work item.  Items of
+// interior tiles run the unmasked instance, boundary tiles (crossing the
+// diagonal or the ragged edge) the masked instance.  With several
+// wavefronts the launch supplies the LDS for their partial sums.
+template <int D, int CPL, int G, bool DBUF, bool VEC4, bool STRESS, bool ACC, int R, int C>
+__global__ __launch_bounds__(WAVE * R * C) void bx_kernel(
     const InstDesc *__restrict__ insts, const StreamItem *__restrict__ items, int cur) {
+    extern __shared__ float smem[];
     const StreamItem it = items[blockIdx.x];
     const InstDesc &b = insts[it.inst];
     if (b.st->done) return;
     const float *Xs = b.Xs[cur];
     const int I = it.tile >> 16, J = it.tile & 0xffff;
     if (it.ftile < b.g.nint)
-        stream_tile<D, CPL, G, DBUF, VEC4, false, STRESS, ACC>(b.g, b.dp, Xs, it.mod, I, J,
-                                                               it.ftile, b.P, b.F);
+        stream_tile<D, CPL, G, DBUF, VEC4, false, STRESS, ACC, R, C>(b.g, b.dp, Xs, it.mod, I, J,
+                                                                     it.ftile, b.P, b.F, smem);
     else
-        stream_tile<D, CPL, G, DBUF, VEC4, true, STRESS, ACC>(b.g, b.dp, Xs, it.mod, I, J,
-                                                              it.ftile, b.P, b.F);
+        stream_tile<D, CPL, G, DBUF, VEC4, true, STRESS, ACC, R, C>(b.g, b.dp, Xs, it.mod, I, J,
+                                                                    it.ftile, b.P, b.F, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -614,38 +677,48 @@ __global__ void to_soa_kernel(TriGeom g, int D, const float *__restrict__ X,
             (j < g.n) ? X[((size_t)a * g.n + j) * D + k] : 0.f;
 }
 
-template <int D, int CPL, int G, bool DBUF, bool VEC4>
+template <int D, int CPL, int G, bool DBUF, bool VEC4, int R, int C>
 hipError_t launch_stream_t(const InstDesc *insts, const StreamItem *items, int nitems,
-                           int cur, bool stress, bool acc, hipStream_t s) {
+                           int cur, bool stress, bool acc, size_t lds, hipStream_t s) {
     if (nitems == 0) return hipSuccess;
-    const dim3 grid((unsigned)nitems), block(WAVE);
+    const dim3 grid((unsigned)nitems), block(WAVE * R * C);
+    if (R * C == 1) lds = 0;
     if (stress && acc)
-        bx_kernel<D, CPL, G, DBUF, VEC4, true, true><<<grid, block, 0, s>>>(insts, items, cur);
+        bx_kernel<D, CPL, G, DBUF, VEC4, true, true, R, C><<<grid, block, lds, s>>>(insts, items,
+                                                                                 cur);
     else if (acc)
-        bx_kernel<D, CPL, G, DBUF, VEC4, false, true><<<grid, block, 0, s>>>(insts, items, cur);
+        bx_kernel<D, CPL, G, DBUF, VEC4, false, true, R, C><<<grid, block, lds, s>>>(insts, items,
+                                                                                  cur);
     else
-        bx_kernel<D, CPL, G, DBUF, VEC4, true, false><<<grid, block, 0, s>>>(insts, items, cur);
+        bx_kernel<D, CPL, G, DBUF, VEC4, true, false, R, C><<<grid, block, lds, s>>>(insts, items,
+                                                                                  cur);
     return hipGetLastError();
 }
 
-template <int D, int CPL, int G, bool DBUF>
+template <int D, int CPL, int G, bool DBUF, int R = 1, int C = 1>
 hipError_t launch_stream_v(int vec4, const InstDesc *insts, const StreamItem *items,
-                           int nitems, int cur, bool stress, bool acc, hipStream_t s) {
-    return vec4 ? launch_stream_t<D, CPL, G, DBUF, true>(insts, items, nitems, cur, stress, acc, s)
-                : launch_stream_t<D, CPL, G, DBUF, false>(insts, items, nitems, cur, stress, acc, s);
+                           int nitems, int cur, bool stress, bool acc, size_t lds,
+                           hipStream_t s) {
+    return vec4 ? launch_stream_t<D, CPL, G, DBUF, true, R, C>(insts, items, nitems, cur, stress,
+                                                               acc, lds, s)
+                : launch_stream_t<D, CPL, G, DBUF, false, R, C>(insts, items, nitems, cur, stress,
+                                                                acc, lds, s);
 }
 
-// Kernel variants (columns per lane, rows per group, double-buffered rows);
-// the numbering is shared with the host's variant table.
+// Kernel variants (columns per lane, rows per group, double-buffered rows,
+// wavefronts per tile R x C); the numbering is shared with the host's
+// variant table.
 template <int D>
 hipError_t launch_stream_d(int variant, int vec4, const InstDesc *insts,
                            const StreamItem *items, int nitems, int cur, bool stress,
-                           bool acc, hipStream_t s) {
+                           bool acc, size_t lds, hipStream_t s) {
     switch (variant) {
-    case 1: return launch_stream_v<D, 4, 8, false>(vec4, insts, items, nitems, cur, stress, acc, s);
-    case 2: return launch_stream_v<D, 8, 4, false>(vec4, insts, items, nitems, cur, stress, acc, s);
-    case 3: return launch_stream_v<D, 8, 8, false>(vec4, insts, items, nitems, cur, stress, acc, s);
-    default: return launch_stream_v<D, 4, 8, true>(vec4, insts, items, nitems, cur, stress, acc, s);
+    case 1: return launch_stream_v<D, 4, 8, false>(vec4, insts, items, nitems, cur, stress, acc, lds, s);
+    case 2: return launch_stream_v<D, 8, 4, false>(vec4, insts, items, nitems, cur, stress, acc, lds, s);
+    case 3: return launch_stream_v<D, 8, 8, false>(vec4, insts, items, nitems, cur, stress, acc, lds, s);
+    case 4: return launch_stream_v<D, 4, 8, false, 4, 1>(vec4, insts, items, nitems, cur, stress, acc, lds, s);
+    case 5: return launch_stream_v<D, 4, 8, false, 2, 2>(vec4, insts, items, nitems, cur, stress, acc, lds, s);
+    default: return launch_stream_v<D, 4, 8, true>(vec4, insts, items, nitems, cur, stress, acc, lds, s);
     }
 }
 
@@ -653,16 +726,16 @@ hipError_t launch_stream_d(int variant, int vec4, const InstDesc *insts,
 
 hipError_t launch_stream(int D, int variant, int vec4, const InstDesc *insts,
                          const StreamItem *items, int nitems, int cur, bool stress,
-                         bool acc, hipStream_t s) {
+                         bool acc, size_t lds, hipStream_t s) {
     switch (D) {
-    case 1: return launch_stream_d<1>(variant, vec4, insts, items, nitems, cur, stress, acc, s);
-    case 2: return launch_stream_d<2>(variant, vec4, insts, items, nitems, cur, stress, acc, s);
-    case 3: return launch_stream_d<3>(variant, vec4, insts, items, nitems, cur, stress, acc, s);
-    case 4: return launch_stream_d<4>(variant, vec4, insts, items, nitems, cur, stress, acc, s);
-    case 5: return launch_stream_d<5>(variant, vec4, insts, items, nitems, cur, stress, acc, s);
-    case 6: return launch_stream_d<6>(variant, vec4, insts, items, nitems, cur, stress, acc, s);
-    case 7: return launch_stream_d<7>(variant, vec4, insts, items, nitems, cur, stress, acc, s);
-    case 8: return launch_stream_d<8>(variant, vec4, insts, items, nitems, cur, stress, acc, s);
+    case 1: return launch_stream_d<1>(variant, vec4, insts, items, nitems, cur, stress, acc, lds, s);
+    case 2: return launch_stream_d<2>(variant, vec4, insts, items, nitems, cur, stress, acc, lds, s);
+    case 3: return launch_stream_d<3>(variant, vec4, insts, items, nitems, cur, stress, acc, lds, s);
+    case 4: return launch_stream_d<4>(variant, vec4, insts, items, nitems, cur, stress, acc, lds, s);
+    case 5: return launch_stream_d<5>(variant, vec4, insts, items, nitems, cur, stress, acc, lds, s);
+    case 6: return launch_stream_d<6>(variant, vec4, insts, items, nitems, cur, stress, acc, lds, s);
+    case 7: return launch_stream_d<7>(variant, vec4, insts, items, nitems, cur, stress, acc, lds, s);
+    case 8: return launch_stream_d<8>(variant, vec4, insts, items, nitems, cur, stress, acc, lds, s);
     default: return hipErrorInvalidValue;
     }
 }

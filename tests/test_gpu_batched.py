@@ -47,7 +47,12 @@ def _rel_fro(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-def test_batch_equals_standalone_and_oracle(ctx):
+@pytest.mark.parametrize("tile", [None, "64:4", "96:5"])
+def test_batch_equals_standalone_and_oracle(ctx, monkeypatch, tile):
+    """Also with every instance forced onto a multi-wavefront tile variant,
+    whose launches size their LDS for the tallest tile of the batch."""
+    if tile:
+        monkeypatch.setenv("FJOFC_TILE", tile)
     insts = _instances(12)
     iters = 40
     dev = [([_dev(x) for x in dl], w, _dev(X0)) for _, dl, w, X0 in insts]

@@ -63,9 +63,13 @@ def _rel_fro(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-def test_config0_parity(ctx):
+@pytest.mark.parametrize("tile", [None, "64:4", "32:5"])
+def test_config0_parity(ctx, monkeypatch, tile):
     """m=2, n=200, d=2, 200 transforms, tol 1e-10 relative, stress every
-    transform: final stress to 1e-5 relative, X to 1e-4 relative Frobenius."""
+    transform: final stress to 1e-5 relative, X to 1e-4 relative Frobenius;
+    with the tuned tiles and with tiles shared by several wavefronts."""
+    if tile:
+        monkeypatch.setenv("FJOFC_TILE", tile)
     P = gen.config0()
     Xo, ro, ho = orc.embed(P.delta, P.wmat, P.X0, P.iters, tol=P.tol, tol_mode=1,
                            stress_every=P.stress_every)
@@ -83,15 +87,21 @@ def test_config0_parity(ctx):
 
 
 @pytest.mark.parametrize("tile", ["256:0", "128:1", "64:2", "512:3", "512:1", "32:1", "16:2",
-                                  "24:1", "96:3", "160:0", "200:2"])
+                                  "24:1", "96:3", "160:0", "200:2",
+                                  "512:4", "96:4", "200:4", "256:5", "48:5",
+                                  "384:1", "384:4"])
 @pytest.mark.parametrize("m,n,d", [(1, 2, 1), (2, 3, 2), (3, 7, 3), (2, 64, 5),
                                    (2, 255, 2), (3, 256, 5), (2, 257, 3),
                                    (4, 300, 8), (2, 513, 4), (3, 1000, 5),
                                    (2, 1030, 6), (2, 777, 7)])
 def test_one_transform_parity(ctx, monkeypatch, tile, m, n, d):
     """One Guttman transform and the stress of X0 and X1, across tile shapes
-    (heights that are powers of two or only multiples of 8), ragged tails (n
-    not a multiple of the tile or of 4) and all d."""
+    (heights that are powers of two or only multiples of 8; one wavefront or
+    R x C wavefronts per tile, including heights rounded up to whole 8-row
+    groups per wavefront), ragged tails (n not a multiple of the tile or of
+    4) and all d.  A height above the tile width that is not a multiple of
+    it gives a row padding that is not a multiple of 256 (n = 513, 777 with
+    height 384), which the commensurability partials must not over-count."""
     monkeypatch.setenv("FJOFC_TILE", tile)
     wmat = _general_wmat(m, seed=n)
     delta, _, X0 = _problem(100 + n + d, m, n, d, wmat=wmat)
