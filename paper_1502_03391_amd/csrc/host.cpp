@@ -454,20 +454,42 @@ struct StreamGroup {
     size_t lds;    // dynamic LDS per workgroup (largest over the group's instances)
 };
 
+// Side streams on which the stream launches of different groups run
+// concurrently: group g > 0 runs on side[g - 1], forked from and joined back
+// to the main stream with events.  Each instance belongs to one group and
+// writes only its own partial sums, so the order of the groups does not
+// change any result.
+struct Fork {
+    std::vector<hipStream_t> side;
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> join;
+};
+
 // Enqueue Algorithm 2's loop for instances advancing in lockstep.  Used
-// eagerly by fjofc_embed and under stream capture by the batched plan.
+// eagerly by fjofc_embed and under stream capture by the batched plan
+// (which passes `fork` so that its groups become parallel graph branches).
 int enqueue_loop(fjofc_ctx *ctx, const InstDesc *insts, int count, int maxm,
                  const std::vector<StreamGroup> &groups, const RowItem *rows, int nrows,
                  int iters, double tol, int tol_mode, int stress_every, int nhist,
-                 bool stress_only, hipStream_t s) {
+                 bool stress_only, hipStream_t s, const Fork *fork = nullptr) {
     HIP_TRY(launch_init(insts, count, nhist, s));
     HIP_TRY(launch_com(insts, rows, nrows, s));
+    const bool forked = fork && groups.size() > 1 && fork->side.size() + 1 >= groups.size();
     auto stream_pass = [&](int cur, bool stress, bool acc) -> int {
-        for (const StreamGroup &gr : groups) {
-            Timed tm(ctx, acc ? K_STREAM : K_EDGE, gr.bytes, s);
+        if (forked) HIP_TRY(hipEventRecord(fork->fork, s));
+        for (size_t q = 0; q < groups.size(); ++q) {
+            const StreamGroup &gr = groups[q];
+            hipStream_t gs = (forked && q > 0) ? fork->side[q - 1] : s;
+            if (gs != s) HIP_TRY(hipStreamWaitEvent(gs, fork->fork, 0));
+            Timed tm(ctx, acc ? K_STREAM : K_EDGE, gr.bytes, gs);
             HIP_TRY(launch_stream(gr.D, gr.variant, gr.vec4, insts, gr.items, gr.nitems, cur,
-                                  stress, acc, gr.lds, s));
+                                  stress, acc, gr.lds, gs));
         }
+        if (forked)
+            for (size_t q = 1; q < groups.size(); ++q) {
+                HIP_TRY(hipEventRecord(fork->join[q - 1], fork->side[q - 1]));
+                HIP_TRY(hipStreamWaitEvent(s, fork->join[q - 1], 0));
+            }
         return FJOFC_OK;
     };
     for (int p = 0; p < iters; ++p) {
@@ -603,6 +625,7 @@ struct fjofc_batch {
     int nrows = 0;
     hipStream_t cs = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    Fork fork;  // side streams for the concurrent stream groups
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int key_iters = -1, key_every = -1, key_mode = -1;
@@ -619,6 +642,9 @@ void batch_free(fjofc_batch *b) {
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
     if (b->cs) (void)hipStreamDestroy(b->cs);
+    for (hipStream_t st : b->fork.side) (void)hipStreamDestroy(st);
+    for (hipEvent_t ev : b->fork.join) (void)hipEventDestroy(ev);
+    if (b->fork.fork) (void)hipEventDestroy(b->fork.fork);
     if (b->mem) (void)hipFree(b->mem);
     if (b->pinned) (void)hipHostFree(b->pinned);
     delete b;
@@ -916,6 +942,25 @@ int fjofc_batch_create(fjofc_ctx *ctx, const fjofc_problem *probs, int count,
                 hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
                 hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess))
         rc = fail(FJOFC_EHIP, "batch stream/event creation failed");
+    // one side stream (default priority) and join event per extra group
+    if (!rc && b->groups.size() > 1) {
+        if (hipEventCreateWithFlags(&b->fork.fork, hipEventDisableTiming) != hipSuccess)
+            rc = fail(FJOFC_EHIP, "batch event creation failed");
+        for (size_t q = 1; !rc && q < b->groups.size(); ++q) {
+            hipStream_t st = nullptr;
+            hipEvent_t ev = nullptr;
+            if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+                rc = fail(FJOFC_EHIP, "batch side stream creation failed");
+                break;
+            }
+            b->fork.side.push_back(st);
+            if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+                rc = fail(FJOFC_EHIP, "batch event creation failed");
+                break;
+            }
+            b->fork.join.push_back(ev);
+        }
+    }
     if (!rc && hipHostMalloc(reinterpret_cast<void **>(&b->pinned), sizeof(EmbedState) * count,
                              hipHostMallocDefault) != hipSuccess) {
         b->pinned = nullptr;
@@ -947,7 +992,7 @@ int fjofc_batch_run(fjofc_batch *b, int iters, double tol, int tol_mode, int str
         ctx->prof = false;  // no event records inside the captured graph
         HIP_TRY(hipStreamBeginCapture(b->cs, hipStreamCaptureModeThreadLocal));
         rc = enqueue_loop(ctx, b->d_insts, b->count, b->maxm, b->groups, b->d_rows, b->nrows,
-                          iters, tol, tol_mode, stress_every, 0, false, b->cs);
+                          iters, tol, tol_mode, stress_every, 0, false, b->cs, &b->fork);
         const hipError_t ec = hipStreamEndCapture(b->cs, &b->graph);
         ctx->prof = prof;
         if (rc) return rc;
