@@ -284,7 +284,10 @@ __device__ __forceinline__ void stream_tile(
     const int thw = g.th / R;
     const int ct0 = tile_col0(g, I, J), rt0 = I * g.th;   // the tile
     const int c0 = ct0 + wc * TWW, r0 = rt0 + wr * thw;   // this wavefront's part
-    const int nr = MASK ? min(thw, n - r0) : thw;
+    // rows to stream; none when the part holds no pair l > j inside n (its
+    // columns start at or beyond n, or its rows are all >= its last column)
+    const bool empty = MASK && (c0 >= n || r0 >= c0 + TWW - 1);
+    const int nr = MASK ? (empty ? 0 : min(thw, n - r0)) : thw;
 
     float xc[CPL][D];
 #pragma unroll
@@ -322,6 +325,14 @@ __device__ __forceinline__ void stream_tile(
     const int rpitch = NW == 1 ? npad : g.th;
     const int rbase = NW == 1 ? r0 : wr * thw;
 
+    if (NW > 1 && ACC && empty) {
+        // the workgroup still adds this wavefront's row sums for the rows
+        // below n: they are zero
+        for (int q = lane; q < D * thw; q += WAVE) {
+            const int k = q / thw, r = q - k * thw;
+            rsink[(size_t)k * rpitch + rbase + r] = 0.f;
+        }
+    }
     if (DBUF) {
         // Two row buffers used alternately (no register copies, so the
         // loads of the next group stay in flight while the current group
