@@ -8,13 +8,15 @@
 // Delta_b is symmetric, so every unordered pair {j,l} is read once, from the
 // strict upper triangle: the pair's term t = r_jl (X_l - X_j) is added to the
 // column accumulator of l and subtracted from the row accumulator of j.  The
-// triangle is cut into th x tw tiles (tw = 64 lanes x CPL columns); one
-// wavefront streams one tile, walking its rows G at a time.  Each lane owns
-// CPL columns of the tile (coalesced 16-byte loads of each row), keeps their
-// column sums in registers for the whole tile, and keeps per-row partial
-// sums for the current G rows; those are reduced across the 64 lanes (a
-// reduce-scatter with permlane swaps and DPP, so each lane finishes one row
-// component) before the next G rows.  The configuration is held in SoA form
+// triangle is cut into th x tw tiles; a workgroup of R x C wavefronts streams
+// one tile, each wavefront a slab of th / R rows and 64 lanes x CPL columns,
+// walking its rows G at a time.  Each lane owns CPL columns (coalesced
+// 16-byte loads of each row), keeps their column sums in registers for the
+// whole slab, and keeps per-row partial sums for the current G rows; those
+// are reduced across the 64 lanes (a reduce-scatter with permlane swaps and
+// DPP, so each lane finishes one row component) before the next G rows.
+// With several wavefronts the slabs' sums meet in LDS and are added in a
+// fixed order at the end of the tile.  The configuration is held in SoA form
 // [m][D][npad] so a group's row points are wave-uniform scalar loads and the
 // column points are vector loads.  Tiles crossing the diagonal or the
 // ragged edge run in a separate masked instance so the interior instance
