@@ -147,6 +147,7 @@ struct OOSArgs {
     int *iters_out;       // optional k
     double tol;
     int iters;
+    int ob;               // objects per workgroup, 1..4 (0: the default, four)
 };
 // colsum: workspace of m * D doubles (sum_j X^(i)_j, computed first).
 hipError_t launch_oos(const OOSArgs &a, double *colsum, hipStream_t s);

@@ -792,6 +792,7 @@ int fjofc_oos(fjofc_ctx *ctx, const float *X_in, int m, int n, int d,
     a.iters_out = iters_out;
     a.tol = tol;
     a.iters = iters;
+    a.ob = 0;  // objects per workgroup chosen from k
     {
         Timed tm(ctx, K_OOS, 4.0 * (double)k * m * n * (iters + 1), s);
         HIP_TRY(launch_oos(a, colsum, s));

@@ -58,10 +58,16 @@ def _run(ctx, X, wmat, dnew, Y0, iters, **kw):
     return Y.cpu().numpy().astype(np.float64), st.cpu().numpy(), it.cpu().numpy()
 
 
+@pytest.mark.parametrize("ob", [None, "1", "2", "4"])
 @pytest.mark.parametrize("m,n,d,k", [(2, 200, 2, 9), (3, 257, 3, 17), (2, 1000, 5, 40),
                                      (1, 100, 2, 8), (4, 64, 8, 5), (2, 3, 1, 3), (8, 300, 3, 6),
                                      (2, 1536, 4, 13)])
-def test_oos_parity(ctx, m, n, d, k):
+def test_oos_parity(ctx, monkeypatch, m, n, d, k, ob):
+    """Against the oracle for 0, 1 and 25 transforms; with the default four
+    objects per workgroup or with 1, 2 or 4 forced (k not a multiple of
+    them leaves a partly filled last workgroup)."""
+    if ob:
+        monkeypatch.setenv("FJOFC_OOS_OB", ob)
     X, wmat, dnew, Y0 = _oos_problem(30 + n, m, n, d, k)
     for iters in (0, 1, 25):
         Yo, so, io = orc.oos(X, wmat, dnew, Y0, iters)
@@ -72,7 +78,10 @@ def test_oos_parity(ctx, m, n, d, k):
         np.testing.assert_allclose(Yg, Yo, rtol=0, atol=1e-4 * scale)
 
 
-def test_oos_target_and_tol_stops(ctx):
+@pytest.mark.parametrize("ob", [None, "1"])
+def test_oos_target_and_tol_stops(ctx, monkeypatch, ob):
+    if ob:
+        monkeypatch.setenv("FJOFC_OOS_OB", ob)
     m, n, d, k = 2, 500, 3, 24
     X, wmat, dnew, Y0 = _oos_problem(77, m, n, d, k)
     _, s50, _ = orc.oos(X, wmat, dnew, Y0, 50)
