@@ -148,6 +148,7 @@ struct OOSArgs {
     double tol;
     int iters;
     int ob;               // objects per workgroup, 1..4 (0: the default, four)
+    int vec4;             // 1: n % 4 == 0 and dnew 16-byte aligned (16-byte loads)
 };
 // colsum: workspace of m * D doubles (sum_j X^(i)_j, computed first).
 hipError_t launch_oos(const OOSArgs &a, double *colsum, hipStream_t s);

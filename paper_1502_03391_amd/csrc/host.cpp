@@ -792,7 +792,9 @@ int fjofc_oos(fjofc_ctx *ctx, const float *X_in, int m, int n, int d,
     a.iters_out = iters_out;
     a.tol = tol;
     a.iters = iters;
-    a.ob = 0;  // objects per workgroup chosen from k
+    a.ob = 0;  // the default objects per workgroup
+    a.vec4 = (n % 4 == 0 && (reinterpret_cast<uintptr_t>(delta_new) & 15) == 0 &&
+              !std::getenv("FJOFC_OOS_SCALAR")) ? 1 : 0;
     {
         Timed tm(ctx, K_OOS, 4.0 * (double)k * m * n * (iters + 1), s);
         HIP_TRY(launch_oos(a, colsum, s));

@@ -93,9 +93,36 @@ def test_oos_target_and_tol_stops(ctx, monkeypatch, ob):
     agree = ig == io
     assert agree.mean() >= 0.9
     np.testing.assert_allclose(sg[agree], so[agree], rtol=1e-5)
+    # The relative-decrease rule compares successive stresses at the 1e-5
+    # scale; the GPU forms them from FP32 partial sums in another order than
+    # the FP64 oracle, so an object whose decrease lies within that noise of
+    # the threshold may stop a transform earlier or later on either side.
+    # Both stops are valid: such objects must end at the oracle's stress up
+    # to the size of one late-stage decrease.
     Yo, so, io = orc.oos(X, wmat, dnew, Y0, 200, tol=1e-5)
     Yg, sg, ig = _run(ctx, X, wmat, dnew, Y0, 200, tol=1e-5)
-    assert (ig == io).mean() >= 0.9
+    same = ig == io
+    assert same.mean() >= 0.75
+    np.testing.assert_allclose(sg[same], so[same], rtol=1e-5)
+    np.testing.assert_allclose(sg[~same], so[~same], rtol=1e-4)
+    assert np.all(np.abs(ig - io) <= 0.25 * io)
+
+
+@pytest.mark.parametrize("m,n,d,k", [(2, 1000, 5, 10), (3, 2048, 3, 7)])
+def test_oos_vector_and_scalar_streams(ctx, monkeypatch, m, n, d, k):
+    """n % 4 == 0 selects the 16-byte stream; FJOFC_OOS_SCALAR forces the
+    4-byte one.  Both against the oracle (they sum in different orders, so
+    they agree with each other only to FP32 rounding)."""
+    X, wmat, dnew, Y0 = _oos_problem(55 + n, m, n, d, k)
+    Yo, so, io = orc.oos(X, wmat, dnew, Y0, 25)
+    scale = np.abs(X).max()
+    for scalar in (False, True):
+        if scalar:
+            monkeypatch.setenv("FJOFC_OOS_SCALAR", "1")
+        Yg, sg, ig = _run(ctx, X, wmat, dnew, Y0, 25)
+        assert np.array_equal(ig, io)
+        np.testing.assert_allclose(sg, so, rtol=1e-5)
+        np.testing.assert_allclose(Yg, Yo, rtol=0, atol=1e-4 * scale)
 
 
 def test_oos_leave_one_out_fixed_point(ctx):
