@@ -33,6 +33,17 @@
  *    diagonal (the library reads only the strict upper triangle j < l).
  *  - Configurations are FP32 row-major: X is (m*n) x d, modality-major
  *    (rows i*n .. i*n+n-1 hold X^(i), Section 1.2.1).
+ *
+ * Tuning overrides (environment variables, read when a problem is planned
+ * or launched; none changes what is computed beyond FP32 summation order):
+ *  - FJOFC_TUNE_TABLE  path of the stream tile table (default:
+ *                      tune_gfx950.txt next to the library);
+ *  - FJOFC_TILE        "th:variant" forces the in-sample tile height and
+ *                      kernel variant (the height is rounded up to whole
+ *                      8-row groups per wavefront);
+ *  - FJOFC_OOS_OB      1..4 objects per out-of-sample workgroup (default 4);
+ *  - FJOFC_OOS_SCALAR  any value: the out-of-sample stream uses 4-byte
+ *                      loads even when n % 4 == 0.
  */
 #ifndef FJOFC_H
 #define FJOFC_H
