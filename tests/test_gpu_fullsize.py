@@ -1,0 +1,128 @@
+"""GPU parity at the benchmark's full sizes, in the launch configurations
+bench.py times, on outputs the oracle can afford: one full in-sample
+transform (the FP64 C oracle does it in well under a second on the host),
+sampled out-of-sample objects (each object is an independent problem), and
+sampled instances of the 512-instance batch (bitwise against standalone
+runs, one small one also against the oracle).  Longer runs are checked
+through properties that hold at any size (the stress history never rises
+beyond FP32 noise)."""
+import numpy as np
+import pytest
+
+from tests.conftest import gpu_available
+from workloads import generators as gen
+
+pytestmark = pytest.mark.gpu
+
+if gpu_available():
+    import torch
+    from paper_1502_03391_amd import fjofc
+    from oracle import structured as orc
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not gpu_available():
+        pytest.skip("no GPU")
+    c = fjofc.Context(0)
+    yield c
+    c.close()
+
+
+def _f32(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def test_insample_full_size_transform_and_history(ctx):
+    """m=3, n=20000, d=5 (4.8 GB of Delta), the tuned tiles: X_1 and the
+    stresses of X_0 and X_1 against the oracle; 30 transforms with stress
+    every 10 never increase it."""
+    spec = gen.config1_spec()
+    views, _, X0 = gen.config1_views(spec)
+    dev = torch.device("cuda:0")
+    delta = [gen.pairwise_dist_torch(Y, dev) for Y in views]
+    host = np.empty((spec.m, spec.n, spec.n), dtype=np.float32)
+    for i in range(spec.m):
+        host[i] = delta[i].cpu().numpy()
+    wmat = gen.uniform_wmat(spec.m, spec.w)
+    X0f = X0.astype(np.float32)
+    X = _f32(X0f)
+    res, hist = fjofc.fjofc_embed(ctx, delta, wmat, X, 1, want_hist=True)
+    torch.cuda.synchronize()
+    X1g = X.cpu().numpy().astype(np.float64)
+    X0c = X0f.astype(np.float64)
+    X1o = orc.guttman(host, wmat, X0c)
+    np.testing.assert_allclose(X1g, X1o, rtol=0, atol=2e-5 * np.abs(X1o).max())
+    assert hist[0] == pytest.approx(orc.stress(host, wmat, X0c)[0], rel=2e-6)
+    assert res["stress"] == pytest.approx(orc.stress(host, wmat, X1o)[0], rel=2e-5)
+    X = _f32(X0f)
+    res, hist = fjofc.fjofc_embed(ctx, delta, wmat, X, 30, stress_every=10, want_hist=True)
+    h = hist[~np.isnan(hist)]
+    assert len(h) == 4 and np.all(np.diff(h) <= 1e-6 * h[:-1])
+    assert res["iters_run"] == 30
+
+
+def test_oos_full_launch_sampled_objects(ctx):
+    """n=10000, m=2, d=5, one launch of 4096 objects, 100 transforms:
+    sampled objects against the oracle run on those objects alone."""
+    sp = gen.config2_spec()
+    dev = torch.device("cuda:0")
+    views, maps, X0 = gen.latent_views(sp.seed_in, sp.n, sp.m, sp.lat, sp.sigma, sp.d)
+    delta = [gen.pairwise_dist_torch(Y, dev) for Y in views]
+    wmat = gen.uniform_wmat(sp.m, sp.w)
+    Xin = _f32(X0)
+    fjofc.fjofc_embed(ctx, delta, wmat, Xin, 50, stress_every=50)
+    del delta
+    k = sp.batch
+    new = gen.oos_objects(sp.seed_new, k, maps, sp.sigma)
+    dnew = torch.empty((k, sp.m, sp.n), dtype=torch.float32, device=dev)
+    for i in range(sp.m):
+        dnew[:, i, :] = gen.cross_dist_torch(new[i], views[i], dev)
+    scale = float(torch.sqrt((Xin.double() ** 2).mean()))
+    Y0 = gen.gaussian_start(sp.seed_start, (k, sp.m, sp.d), scale).astype(np.float32)
+    Y = _f32(Y0)
+    st = torch.empty(k, dtype=torch.float64, device=dev)
+    it = torch.empty(k, dtype=torch.int32, device=dev)
+    fjofc.fjofc_oos(ctx, Xin, wmat, dnew, Y, sp.iters, stress_out=st, iters_out=it)
+    torch.cuda.synchronize()
+    pick = np.random.default_rng(5).choice(k, 12, replace=False)
+    Xh = Xin.cpu().numpy().astype(np.float64)
+    Yo, so, io = orc.oos(Xh, wmat, dnew[pick].cpu().numpy(), Y0[pick].astype(np.float64),
+                         sp.iters)
+    Yg = Y.cpu().numpy()[pick].astype(np.float64)
+    assert np.array_equal(it.cpu().numpy()[pick], io)
+    np.testing.assert_allclose(st.cpu().numpy()[pick], so, rtol=1e-5)
+    np.testing.assert_allclose(Yg, Yo, rtol=0, atol=1e-4 * np.abs(Xh).max())
+
+
+def test_batched_full_batch_sampled_instances(ctx):
+    """The 512 uneven instances of the batched workload, 20 transforms from
+    one graph: sampled instances bitwise equal to standalone runs, and the
+    smallest sampled one against the oracle."""
+    dev = torch.device("cuda:0")
+    specs = gen.batched_specs(512)
+    probs, X0s, hosts = [], [], []
+    for sp in specs:
+        views, _, X0 = gen.instance_views(sp)
+        probs.append(([gen.pairwise_dist_torch(Y, dev) for Y in views],
+                      gen.uniform_wmat(sp.m, 0.5), _f32(X0)))
+        X0s.append(X0.astype(np.float32))
+    b = fjofc.Batch(ctx, probs)
+    iters = 20
+    res = b.run(iters, stress_every=iters)
+    torch.cuda.synchronize()
+    pick = np.random.default_rng(9).choice(len(specs), 6, replace=False)
+    for p in pick:
+        dl, w, Xb = probs[p]
+        Xs = _f32(X0s[p])
+        rs, _ = fjofc.fjofc_embed(ctx, dl, w, Xs, iters, stress_every=iters)
+        assert torch.equal(Xb, Xs), f"instance {p} differs from standalone"
+        assert res[p]["stress"] == rs["stress"]
+    small = min(pick, key=lambda p: specs[p].n * specs[p].m)
+    dl, w, Xb = probs[small]
+    host = [x.cpu().numpy() for x in dl]
+    Xo, ro, _ = orc.embed(host, w, X0s[small].astype(np.float64), iters, stress_every=iters)
+    assert res[small]["stress"] == pytest.approx(ro["stress"], rel=1e-5)
+    Xg = Xb.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo) <= 1e-4
+    b.close()
