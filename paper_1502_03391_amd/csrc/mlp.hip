@@ -10,6 +10,8 @@
 // product operands are stored in BF16; accumulation is FP32.
 #include "fjofc_internal.h"
 
+#include <cstdlib>
+
 #include <algorithm>
 
 namespace fjofc {
@@ -36,9 +38,10 @@ __device__ __forceinline__ float gelu_grad(float z) {
 // C (M x N) = A (M x K) B (K x N), both operands k-contiguous: A(m, k) =
 // A[m lda + k], B(k, n) = Bt[n ldb + k] (the library keeps transposed BF16
 // copies of weights, activations and gradients, so every product reads
-// both operands this way).  A workgroup of four wavefronts covers 64 x 64
-// outputs, each wavefront 32 x 32 as 2 x 2 tiles of the gfx950 BF16 matrix
-// instruction 16x16x32 (FP32 accumulation).  Operand layout of that
+// both operands this way).  A workgroup of 2 x 2 wavefronts covers 64 x 64
+// outputs (one wavefront, 32 x 32, for small products), each wavefront
+// 32 x 32 as 2 x 2 tiles of the gfx950 BF16 matrix instruction 16x16x32
+// (FP32 accumulation).  Operand layout of that
 // instruction: lane l supplies A[l % 16][8 (l / 16) + e] and
 // B[8 (l / 16) + e][l % 16], e = 0..7 (16 contiguous bytes of a k-row), and
 // receives C[4 (l / 16) + v][l % 16], v = 0..3.  Fragments are loaded
@@ -69,13 +72,16 @@ __device__ __forceinline__ bf8 load_frag(const uint16_t *__restrict__ p, long ld
     return f.v;
 }
 
-template <int EPI, bool VEC>
-__global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K,
-                                                   const uint16_t *__restrict__ A, long lda,
-                                                   const uint16_t *__restrict__ Bt, long ldb,
-                                                   GemmEpi e) {
+// WM x WN wavefronts per workgroup (a 32 WM x 32 WN output tile).
+template <int EPI, bool VEC, int WM, int WN>
+__global__ __launch_bounds__(WAVE *WM *WN) void gemm_kernel(int M, int N, int K,
+                                                            const uint16_t *__restrict__ A,
+                                                            long lda,
+                                                            const uint16_t *__restrict__ Bt,
+                                                            long ldb, GemmEpi e) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int m0 = blockIdx.y * GB + (wv >> 1) * 32, n0 = blockIdx.x * GB + (wv & 1) * 32;
+    const int m0 = blockIdx.y * (32 * WM) + (wv / WN) * 32;
+    const int n0 = blockIdx.x * (32 * WN) + (wv % WN) * 32;
     const int li = lane & 15, lk = (lane >> 4) * 8;
     f4 acc[2][2];
 #pragma unroll
@@ -321,25 +327,51 @@ hipError_t launch_broadcast(const float *out, int B, int m, int d, int P, float 
     return hipGetLastError();
 }
 
-template <int EPI>
-static hipError_t gemm_epi(bool vec, dim3 grid, int M, int N, int K, const uint16_t *A, long lda,
+template <int EPI, int WM, int WN>
+static hipError_t gemm_epi(bool vec, int M, int N, int K, const uint16_t *A, long lda,
                            const uint16_t *Bt, long ldb, const GemmEpi &e, hipStream_t s) {
-    if (vec) gemm_kernel<EPI, true><<<grid, 256, 0, s>>>(M, N, K, A, lda, Bt, ldb, e);
-    else gemm_kernel<EPI, false><<<grid, 256, 0, s>>>(M, N, K, A, lda, Bt, ldb, e);
+    const dim3 grid((unsigned)((N + 32 * WN - 1) / (32 * WN)),
+                    (unsigned)((M + 32 * WM - 1) / (32 * WM)));
+    if (vec)
+        gemm_kernel<EPI, true, WM, WN><<<grid, WAVE * WM * WN, 0, s>>>(M, N, K, A, lda, Bt, ldb, e);
+    else
+        gemm_kernel<EPI, false, WM, WN><<<grid, WAVE * WM * WN, 0, s>>>(M, N, K, A, lda, Bt, ldb, e);
     return hipGetLastError();
+}
+
+template <int EPI>
+static hipError_t gemm_waves(bool wide, bool vec, int M, int N, int K, const uint16_t *A,
+                             long lda, const uint16_t *Bt, long ldb, const GemmEpi &e,
+                             hipStream_t s) {
+    return wide ? gemm_epi<EPI, 2, 2>(vec, M, N, K, A, lda, Bt, ldb, e, s)
+                : gemm_epi<EPI, 1, 1>(vec, M, N, K, A, lda, Bt, ldb, e, s);
+}
+
+// Workgroups of 2 x 2 wavefronts (64 x 64 outputs) when that already gives
+// at least two workgroups per CU; otherwise one wavefront per 32 x 32
+// tile, so that the same wavefronts spread over all CUs.  FJOFC_GEMM_WAVES
+// ("1" or "4") forces one of the two.
+constexpr long GEMM_WIDE_MIN_TILES = 512;
+
+bool gemm_wide(int M, int N) {
+    if (const char *v = std::getenv("FJOFC_GEMM_WAVES")) {
+        if (v[0] == '1') return false;
+        if (v[0] == '4') return true;
+    }
+    return (long)((M + GB - 1) / GB) * ((N + GB - 1) / GB) >= GEMM_WIDE_MIN_TILES;
 }
 
 hipError_t launch_gemm(int epi, int M, int N, int K, const uint16_t *A, long lda,
                        const uint16_t *Bt, long ldb, const GemmEpi &e, hipStream_t s) {
     if (M <= 0 || N <= 0) return hipSuccess;
-    const dim3 grid((unsigned)((N + GB - 1) / GB), (unsigned)((M + GB - 1) / GB));
+    const bool wide = gemm_wide(M, N);
     const bool vec = (lda % 8 == 0) && (ldb % 8 == 0) &&
                      ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(Bt)) & 15) == 0;
     switch (epi) {
-    case GEMM_HIDDEN: return gemm_epi<GEMM_HIDDEN>(vec, grid, M, N, K, A, lda, Bt, ldb, e, s);
-    case GEMM_LAST: return gemm_epi<GEMM_LAST>(vec, grid, M, N, K, A, lda, Bt, ldb, e, s);
-    case GEMM_BWD: return gemm_epi<GEMM_BWD>(vec, grid, M, N, K, A, lda, Bt, ldb, e, s);
-    default: return gemm_epi<GEMM_STORE>(vec, grid, M, N, K, A, lda, Bt, ldb, e, s);
+    case GEMM_HIDDEN: return gemm_waves<GEMM_HIDDEN>(wide, vec, M, N, K, A, lda, Bt, ldb, e, s);
+    case GEMM_LAST: return gemm_waves<GEMM_LAST>(wide, vec, M, N, K, A, lda, Bt, ldb, e, s);
+    case GEMM_BWD: return gemm_waves<GEMM_BWD>(wide, vec, M, N, K, A, lda, Bt, ldb, e, s);
+    default: return gemm_waves<GEMM_STORE>(wide, vec, M, N, K, A, lda, Bt, ldb, e, s);
     }
 }
 
