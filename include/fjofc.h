@@ -43,7 +43,9 @@
  *                      8-row groups per wavefront);
  *  - FJOFC_OOS_OB      1..4 objects per out-of-sample workgroup (default 4);
  *  - FJOFC_OOS_SCALAR  any value: the out-of-sample stream uses 4-byte
- *                      loads even when n % 4 == 0.
+ *                      loads even when n % 4 == 0;
+ *  - FJOFC_GEMM_WAVES  "1" or "4": wavefronts per workgroup of the network's
+ *                      matrix products (default: by product size).
  */
 #ifndef FJOFC_H
 #define FJOFC_H
