@@ -343,6 +343,10 @@ int plan_instance(const float *const *delta, int m, int n, const double *wmat, i
         return fail(FJOFC_EINVAL, "internal: row padding %d does not cover n=%d", g.npad, n);
     g.ntr = (n + g.th - 1) / g.th;
     g.ntc = (n + g.tw - 1) / g.tw;
+    // a stream item packs its tile as (I << 16) | J
+    if (g.ntr > 65535 || g.ntc > 65535)
+        return fail(FJOFC_EINVAL, "n=%d needs more than 65535 tile rows or columns of %d x %d",
+                    n, g.th, g.tw);
     bool al = (n % 4) == 0;
     for (int i = 0; i < m; ++i)
         if ((reinterpret_cast<uintptr_t>(delta[i]) & 15) != 0) al = false;
