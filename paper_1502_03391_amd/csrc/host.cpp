@@ -282,11 +282,13 @@ void choose_tiles(int n, int d, int &th, int &variant) {
     th = (th + unit - 1) / unit * unit;
 }
 
-// Dynamic LDS of one stream workgroup: the row sums [C][D][th], column sums
-// [R][D][tw] and one double per wavefront (none with a single wavefront).
+// Dynamic LDS of one stream workgroup.  One wavefront: its row-reduction
+// buffer [4 D][64].  Several: the row sums [C][D][th], column sums [R][D][tw]
+// (which also hold the wavefronts' reduction buffers during the stream) and
+// one double per wavefront.
 size_t stream_lds(const TriGeom &g, int D) {
     const Variant &v = kVariants[g.variant];
-    if (v.r * v.c == 1) return 0;
+    if (v.r * v.c == 1) return (size_t)4 * D * WAVE * sizeof(float);
     return ((size_t)v.c * g.th + (size_t)v.r * g.tw) * D * sizeof(float) +
            (size_t)v.r * v.c * sizeof(double);
 }

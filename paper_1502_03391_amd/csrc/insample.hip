@@ -12,9 +12,11 @@
 // one tile, each wavefront a slab of th / R rows and 64 lanes x CPL columns,
 // walking its rows G at a time.  Each lane owns CPL columns (coalesced
 // 16-byte loads of each row), keeps their column sums in registers for the
-// whole slab, and keeps per-row partial sums for the current G rows; those
-// are reduced across the 64 lanes (a reduce-scatter with permlane swaps and
-// DPP, so each lane finishes one row component) before the next G rows.
+// whole slab, and keeps per-row partial sums for the current rows; every
+// four rows those are summed across the 64 lanes through a small LDS buffer
+// of the wavefront (each lane adds an eight-lane chunk of a few row
+// components, then DPP adds the eight chunks) and each component is stored
+// once.
 // With several wavefronts the slabs' sums meet in LDS and are added in a
 // fixed order at the end of the tile.  The configuration is held in SoA form
 // [m][D][npad] so a group's row points are wave-uniform scalar loads and the
@@ -34,12 +36,6 @@
 
 namespace fjofc {
 namespace {
-
-__device__ __forceinline__ float shfl_xor_f(float v, int mask) {
-    const int lane = threadIdx.x & (WAVE - 1);
-    return __int_as_float(
-        __builtin_amdgcn_ds_bpermute((lane ^ mask) << 2, __float_as_int(v)));
-}
 
 __device__ __forceinline__ double shfl_xor_d(double v, int mask) {
     const int lane = threadIdx.x & (WAVE - 1);
@@ -65,25 +61,10 @@ typedef const __attribute__((address_space(4))) float cfloat;
 constexpr int DPP_QP_XOR1 = 0xB1;        // quad_perm [1,0,3,2]
 constexpr int DPP_QP_XOR2 = 0x4E;        // quad_perm [2,3,0,1]
 constexpr int DPP_ROW_HALF_MIRROR = 0x141;
-constexpr int DPP_ROW_MIRROR = 0x140;
-constexpr int DPP_ROW_ROR8 = 0x128;
 
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-
-// Swap halves: returns the sum that lanes 0-31 keep for `a` and lanes 32-63
-// keep for `b` (each summed over the two 32-lane halves).
-__device__ __forceinline__ float swap32_add(float a, float b) {
-    auto s = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
-    return __uint_as_float(s[0]) + __uint_as_float(s[1]);
-}
-// Same on 16-lane rows: even rows keep `a`, odd rows keep `b`, each summed
-// over the row pair.
-__device__ __forceinline__ float swap16_add(float a, float b) {
-    auto s = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
-    return __uint_as_float(s[0]) + __uint_as_float(s[1]);
 }
 
 // Column of the tile owned by `lane` for its q-th column (q < CPL).
@@ -94,63 +75,54 @@ __device__ __forceinline__ int lane_col(int lane, int q) {
     return VEC4 ? (q >> 2) * 256 + lane * 4 + (q & 3) : lane + WAVE * q;
 }
 
-// Reduce the G rows' partial sums p[G][D] over the 64 lanes and store each
-// row component from one lane.  Lane bit 5 and bit 4 are reduce-scattered
-// with permlane swaps (each halves the rows a lane holds); for G = 8 lane
-// bit 3 is scattered with a DPP rotate; the remaining low lane bits are
-// summed fully with DPP.  Each lane then holds one row's D sums and stores
-// the component selected by its low lane bits.
-template <int D, int G>
-__device__ __forceinline__ void reduce_rows_store(float (&p)[G][D], int lane,
-                                                  float *prow, int npad,
-                                                  int j0, int nvalid) {
-    constexpr int H1 = G / 2, H2 = G / 4;
-    float a[H1][D];
+// Orders this wavefront's LDS accesses (compiler and hardware): LDS
+// operations of one wavefront complete in issue order, so a fence at
+// wavefront scope is all that is needed.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Reduce the partial sums p[4][D] of four rows over the 64 lanes through
+// this wavefront's LDS buffer red[4 D][64] and store each row component
+// once.  Every lane writes its 4 D partials; lane (ob, c) = (lane / 8,
+// lane % 8) then adds, for each of its T = ceil(4 D / 8) outputs ob T + t,
+// the partials of lanes 8c .. 8c+7 (two 16-byte reads, taken in swapped
+// order by odd ob so the two halves of a read fall in disjoint banks), and
+// three DPP steps add the eight chunks, leaving the sum in all eight lanes
+// of the group; lane c of the group stores output ob T + c.
+template <int D>
+__device__ __forceinline__ void reduce4_lds(const float (&p)[4][D], float *red, int lane,
+                                            float *rsink, int rpitch, int rbase, int nvalid) {
+    constexpr int V = 4 * D, T = (V + 7) / 8;
 #pragma unroll
-    for (int r = 0; r < H1; ++r)
+    for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int k = 0; k < D; ++k) a[r][k] = swap32_add(p[r][k], p[r + H1][k]);
-    float b[H2][D];
+        for (int k = 0; k < D; ++k) red[(r * D + k) * WAVE + lane] = p[r][k];
+    wave_sync();
+    const int ob = lane >> 3, c = lane & 7;
+    const int h0 = (ob & 1) * 4;
+    float s[T];
 #pragma unroll
-    for (int r = 0; r < H2; ++r)
-#pragma unroll
-        for (int k = 0; k < D; ++k) b[r][k] = swap16_add(a[r][k], a[r + H2][k]);
-    float c[D];
-    int row, kk;
-    if constexpr (G == 8) {
-        const bool b3 = lane & 8;
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            const float send = b3 ? b[0][k] : b[1][k];
-            const float keep = b3 ? b[1][k] : b[0][k];
-            c[k] = keep + dpp<DPP_ROW_ROR8>(send);
-        }
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            c[k] += dpp<DPP_QP_XOR1>(c[k]);
-            c[k] += dpp<DPP_QP_XOR2>(c[k]);
-            c[k] += dpp<DPP_ROW_HALF_MIRROR>(c[k]);
-        }
-        row = ((lane >> 5) & 1) * 4 + ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1);
-        kk = lane & 7;
-    } else {
-        static_assert(G == 4, "G is 4 or 8");
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            c[k] = b[0][k];
-            c[k] += dpp<DPP_QP_XOR1>(c[k]);
-            c[k] += dpp<DPP_QP_XOR2>(c[k]);
-            c[k] += dpp<DPP_ROW_HALF_MIRROR>(c[k]);
-            c[k] += dpp<DPP_ROW_MIRROR>(c[k]);
-        }
-        row = ((lane >> 5) & 1) * 2 + ((lane >> 4) & 1);
-        kk = lane & 15;
+    for (int t = 0; t < T; ++t) {
+        const int o = min(ob * T + t, V - 1);
+        const float4 a = *reinterpret_cast<const float4 *>(red + o * WAVE + 8 * c + h0);
+        const float4 b = *reinterpret_cast<const float4 *>(red + o * WAVE + 8 * c + (4 - h0));
+        s[t] = ((a.x + a.y) + (a.z + a.w)) + ((b.x + b.y) + (b.z + b.w));
     }
-    float v = c[0];
+    wave_sync();
 #pragma unroll
-    for (int k = 1; k < D; ++k)
-        if (kk == k) v = c[k];
-    if (kk < D && row < nvalid) prow[(size_t)kk * npad + j0 + row] = v;
+    for (int t = 0; t < T; ++t) {
+        s[t] += dpp<DPP_QP_XOR1>(s[t]);
+        s[t] += dpp<DPP_QP_XOR2>(s[t]);
+        s[t] += dpp<DPP_ROW_HALF_MIRROR>(s[t]);
+    }
+    float v = s[0];
+#pragma unroll
+    for (int t = 1; t < T; ++t) v = c == t ? s[t] : v;
+    const int o = ob * T + c, r = o / D, k = o - r * D;
+    if (c < T && o < V && r < nvalid) rsink[(size_t)k * rpitch + rbase + r] = v;
 }
 
 template <int CPL, int G, bool VEC4, bool MASK>
@@ -189,12 +161,14 @@ __device__ __forceinline__ void load_rows(float (&dv)[G][CPL],
 }
 
 // Terms of G rows (given in dv) against the lane's CPL columns.  The G row
-// sums go to rsink[k * rpitch + rbase + g0 + row].
+// sums go to rsink[k * rpitch + rbase + g0 + row], four rows at a time
+// through the wavefront's LDS buffer red.
 template <int D, int CPL, int G, bool VEC4, bool MASK, bool STRESS, bool ACC>
 __device__ __forceinline__ void process_group(
     const float (&dv)[G][CPL], const float *__restrict__ X, int n, int npad,
     int r0, int c0, int g0, int nr, int lane, const float (&xc)[CPL][D],
-    float (&cacc)[CPL][D], float *rsink, int rpitch, int rbase, double &fid) {
+    float (&cacc)[CPL][D], float *rsink, int rpitch, int rbase, float *red, double &fid) {
+    static_assert(G % 4 == 0, "rows are reduced four at a time");
     const int nv = MASK ? min(G, nr - g0) : G;
     // the group's row points (wave-uniform scalar loads; padding rows are 0)
     float xr[G][D];
@@ -253,9 +227,11 @@ __device__ __forceinline__ void process_group(
                 for (int k = 0; k < D; ++k) asm volatile("" : "+v"(cacc[q][k]));
         }
         if (STRESS) asm volatile("" : "+v"(fs));
+        if (ACC && rr % 4 == 3)
+            reduce4_lds<D>(*reinterpret_cast<float(*)[4][D]>(&p[rr - 3][0]), red, lane, rsink,
+                           rpitch, rbase + g0 + rr - 3, nv - (rr - 3));
         __builtin_amdgcn_sched_barrier(0);
     }
-    if (ACC) reduce_rows_store<D, G>(p, lane, rsink, rpitch, rbase + g0, nv);
     if (STRESS) fid += (double)fs;
 }
 
@@ -326,6 +302,11 @@ __device__ __forceinline__ void stream_tile(
     float *rsink = NW == 1 ? prow : srow + (size_t)wc * D * g.th;
     const int rpitch = NW == 1 ? npad : g.th;
     const int rbase = NW == 1 ? r0 : wr * thw;
+    // this wavefront's row-reduction buffer [4 D][64]: the whole LDS with one
+    // wavefront, else a slice of the column-sum region, which takes column
+    // sums only after every wavefront's stream has finished
+    static_assert(NW == 1 || CPL >= 4, "the reduction buffers fit the column region");
+    float *red = NW == 1 ? smem : scol + (size_t)w * 4 * D * WAVE;
 
     if (NW > 1 && ACC && empty) {
         // the workgroup still adds this wavefront's row sums for the rows
@@ -346,14 +327,14 @@ __device__ __forceinline__ void stream_tile(
                 load_rows<CPL, G, VEC4, MASK>(db, dl, n, r0 + g0 + G, c0, lane, nr - g0 - G);
             process_group<D, CPL, G, VEC4, MASK, STRESS, ACC>(da, X, n, npad, r0, c0, g0, nr,
                                                               lane, xc, cacc, rsink, rpitch,
-                                                              rbase, fid);
+                                                              rbase, red, fid);
             if (g0 + G >= nr) break;
             if (g0 + 2 * G < nr)
                 load_rows<CPL, G, VEC4, MASK>(da, dl, n, r0 + g0 + 2 * G, c0, lane,
                                               nr - g0 - 2 * G);
             process_group<D, CPL, G, VEC4, MASK, STRESS, ACC>(db, X, n, npad, r0, c0, g0 + G,
                                                               nr, lane, xc, cacc, rsink, rpitch,
-                                                              rbase, fid);
+                                                              rbase, red, fid);
         }
     } else {
         // One row buffer: other wavefronts on the SIMD cover the load latency.
@@ -362,9 +343,10 @@ __device__ __forceinline__ void stream_tile(
             load_rows<CPL, G, VEC4, MASK>(da, dl, n, r0 + g0, c0, lane, nr - g0);
             process_group<D, CPL, G, VEC4, MASK, STRESS, ACC>(da, X, n, npad, r0, c0, g0, nr,
                                                               lane, xc, cacc, rsink, rpitch,
-                                                              rbase, fid);
+                                                              rbase, red, fid);
         }
     }
+    if constexpr (NW > 1) __syncthreads();
     if (ACC) {
         // this wavefront's column sums: to the partial buffer, or to LDS
         float *csink = NW == 1 ? pcol + c0 : scol + (size_t)wr * D * tw + wc * TWW;
@@ -695,7 +677,6 @@ hipError_t launch_stream_t(const InstDesc *insts, const StreamItem *items, int n
                            int cur, bool stress, bool acc, size_t lds, hipStream_t s) {
     if (nitems == 0) return hipSuccess;
     const dim3 grid((unsigned)nitems), block(WAVE * R * C);
-    if (R * C == 1) lds = 0;
     if (stress && acc)
         bx_kernel<D, CPL, G, DBUF, VEC4, true, true, R, C><<<grid, block, lds, s>>>(insts, items,
                                                                                  cur);
