@@ -458,6 +458,10 @@ struct StreamGroup {
     int nitems;
     double bytes;  // algorithmic bytes of one launch
     size_t lds;    // dynamic LDS per workgroup (largest over the group's instances)
+    // finalize work of the group's instances (a contiguous range of the
+    // row items) and their largest m
+    const RowItem *rows;
+    int nrows, maxm;
 };
 
 // Side streams on which the stream launches of different groups run
@@ -481,7 +485,9 @@ int enqueue_loop(fjofc_ctx *ctx, const InstDesc *insts, int count, int maxm,
     HIP_TRY(launch_init(insts, count, nhist, s));
     HIP_TRY(launch_com(insts, rows, nrows, s));
     const bool forked = fork && groups.size() > 1 && fork->side.size() + 1 >= groups.size();
-    auto stream_pass = [&](int cur, bool stress, bool acc) -> int {
+    // fin_com >= 0: each group's finalize (want_com = fin_com) follows its
+    // stream launch on the group's branch
+    auto stream_pass = [&](int cur, bool stress, bool acc, int fin_com) -> int {
         if (forked) HIP_TRY(hipEventRecord(fork->fork, s));
         for (size_t q = 0; q < groups.size(); ++q) {
             const StreamGroup &gr = groups[q];
@@ -490,6 +496,10 @@ int enqueue_loop(fjofc_ctx *ctx, const InstDesc *insts, int count, int maxm,
             Timed tm(ctx, acc ? K_STREAM : K_EDGE, gr.bytes, gs);
             HIP_TRY(launch_stream(gr.D, gr.variant, gr.vec4, insts, gr.items, gr.nitems, cur,
                                   stress, acc, gr.lds, gs));
+            if (fin_com >= 0) {
+                Timed tf(ctx, K_FIN, 0.0, gs);
+                HIP_TRY(launch_finalize(gr.maxm, insts, gr.rows, gr.nrows, cur, fin_com != 0, gs));
+            }
         }
         if (forked)
             for (size_t q = 1; q < groups.size(); ++q) {
@@ -500,19 +510,26 @@ int enqueue_loop(fjofc_ctx *ctx, const InstDesc *insts, int count, int maxm,
     };
     for (int p = 0; p < iters; ++p) {
         const bool due = (p % stress_every) == 0;
-        int rc = stream_pass(p & 1, due, true);
+        const bool next_due = ((p + 1) % stress_every) == 0 || (p + 1) == iters;
+        // A transform without a stress test has nothing that needs every
+        // group's stream before the finalize (no stop test can end an
+        // instance), so with concurrent groups each group's finalize runs
+        // on its own branch and overlaps the other groups' streams.  Rows
+        // are independent, so the results do not change.
+        const bool branch_fin = forked && !due;
+        int rc = stream_pass(p & 1, due, true, branch_fin ? (next_due ? 1 : 0) : -1);
         if (rc) return rc;
+        if (branch_fin) continue;
         if (due) {
             Timed tm(ctx, K_RED, 0.0, s);
             HIP_TRY(launch_reduce(insts, count, p, 1, 0, iters, tol, tol_mode, s));
         }
-        const bool next_due = ((p + 1) % stress_every) == 0 || (p + 1) == iters;
         Timed tm(ctx, K_FIN, 0.0, s);
         HIP_TRY(launch_finalize(maxm, insts, rows, nrows, p & 1, next_due, s));
     }
     // stress of the returned configuration (and the checkpoint test at
     // t = iters) unless the stop rule already fired.
-    int rc = stream_pass(iters & 1, true, false);
+    int rc = stream_pass(iters & 1, true, false, -1);
     if (rc) return rc;
     {
         Timed tm(ctx, K_RED, 0.0, s);
@@ -569,8 +586,8 @@ int run_insample(fjofc_ctx *ctx, const float *const *delta, int m, int n,
     HIP_TRY(hipMemcpyAsync(const_cast<double *>(desc.wmat), wmat, sizeof(double) * m * m,
                            hipMemcpyHostToDevice, s));
     const double bytes = 4.0 * m * 0.5 * n * (n - 1.0);
-    std::vector<StreamGroup> groups{
-        {d, h.g.variant, h.g.vec4, d_items, (int)items.size(), bytes, stream_lds(h.g, d)}};
+    std::vector<StreamGroup> groups{{d, h.g.variant, h.g.vec4, d_items, (int)items.size(), bytes,
+                                     stream_lds(h.g, d), d_rows, (int)rows.size(), m}};
     rc = enqueue_loop(ctx, d_desc, 1, m, groups, d_rows, (int)rows.size(), iters, tol, tol_mode,
                       stress_every, iters + 1, stress_only, s);
     if (rc) return rc;
@@ -888,6 +905,7 @@ int fjofc_batch_create(fjofc_ctx *ctx, const fjofc_problem *probs, int count,
     std::map<std::tuple<int, int, int>, std::vector<StreamItem>> gitems, gbnd;
     std::map<std::tuple<int, int, int>, double> gbytes;
     std::map<std::tuple<int, int, int>, size_t> glds;
+    std::map<std::tuple<int, int, int>, std::vector<int>> ginst;
     std::vector<RowItem> rows;
     // largest problems first within each group: long items start early
     std::vector<int> order(count);
@@ -902,9 +920,22 @@ int fjofc_batch_create(fjofc_ctx *ctx, const fjofc_problem *probs, int count,
         append_items(p, h, gitems[key], &gbnd[key]);
         gbytes[key] += 4.0 * h.g.m * 0.5 * h.g.n * (h.g.n - 1.0);
         glds[key] = std::max(glds[key], stream_lds(h.g, h.D));
+        ginst[key].push_back(p);
     }
     for (auto &kv : gitems) kv.second.insert(kv.second.end(), gbnd[kv.first].begin(), gbnd[kv.first].end());
-    for (int p = 0; p < count; ++p) append_rows(p, b->hi[p], rows);
+    // row items grouped like the stream items, so each group's finalize
+    // work is one contiguous range
+    std::map<std::tuple<int, int, int>, std::array<int, 3>> grows;  // offset, count, max m
+    for (auto &kv : ginst) {
+        std::sort(kv.second.begin(), kv.second.end());
+        std::array<int, 3> r{(int)rows.size(), 0, 0};
+        for (int p : kv.second) {
+            append_rows(p, b->hi[p], rows);
+            r[2] = std::max(r[2], b->hi[p].g.m);
+        }
+        r[1] = (int)rows.size() - r[0];
+        grows[kv.first] = r;
+    }
     Carve cv;
     const size_t o_insts = cv.take<InstDesc>(count);
     const size_t o_st = cv.take<EmbedState>(count);
@@ -937,14 +968,16 @@ int fjofc_batch_create(fjofc_ctx *ctx, const fjofc_problem *probs, int count,
              sizeof(double) * b->hi[p].wmat.size());
     }
     copy(b->d_insts, descs.data(), sizeof(InstDesc) * count);
+    b->d_rows = reinterpret_cast<RowItem *>(base + o_rows);
     size_t gi = 0;
     for (auto &kv : gitems) {
         StreamItem *d = reinterpret_cast<StreamItem *>(base + o_groups[gi++]);
         copy(d, kv.second.data(), kv.second.size() * sizeof(StreamItem));
+        const std::array<int, 3> &r = grows[kv.first];
         b->groups.push_back({std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
-                             d, (int)kv.second.size(), gbytes[kv.first], glds[kv.first]});
+                             d, (int)kv.second.size(), gbytes[kv.first], glds[kv.first],
+                             b->d_rows + r[0], r[1], r[2]});
     }
-    b->d_rows = reinterpret_cast<RowItem *>(base + o_rows);
     b->nrows = (int)rows.size();
     copy(b->d_rows, rows.data(), rows.size() * sizeof(RowItem));
     if (!rc && (hipStreamCreate(&b->cs) != hipSuccess ||
