@@ -110,6 +110,32 @@ def test_batch_per_instance_stop_rule(ctx):
             assert r["iters_run"] == t and r["converged"] == ro["converged"]
 
 
+def test_batch_stop_rule_between_stress_checks(ctx):
+    """Stop rules tested every third transform.  The transforms in between
+    run each group's finalize on the group's own graph branch, and an
+    instance that has stopped must be left alone there.  Every instance
+    stops at the same transform, with bitwise the same X and stress, as a
+    standalone run (which has a single group and no branches).  With these
+    draws two of the eight instances stop early (the oracle stops them
+    after 90 and 174 transforms)."""
+    insts = _instances(8, seed=17, n_lo=40, n_hi=600)
+    dev = [([_dev(x) for x in dl], w, _dev(X0)) for _, dl, w, X0 in insts]
+    iters = 300
+    b = fjofc.Batch(ctx, dev)
+    res = b.run(iters, tol=1e-4, tol_mode=1, stress_every=3)
+    torch.cuda.synchronize()
+    stopped = 0
+    for (sp, dl, w, X0), (dd, _, Xb), r in zip(insts, dev, res):
+        Xs = _dev(X0)
+        rs, _ = fjofc.fjofc_embed(ctx, dd, w, Xs, iters, tol=1e-4, tol_mode=1, stress_every=3)
+        assert r["iters_run"] == rs["iters_run"] and r["converged"] == rs["converged"]
+        assert r["stress"] == rs["stress"]
+        assert torch.equal(Xb, Xs), f"instance {sp.idx} differs from standalone"
+        stopped += r["iters_run"] < iters
+    assert stopped >= 1
+    b.close()
+
+
 def test_batch_rejects_bad_problem(ctx):
     insts = _instances(3, seed=2)
     dev = [([_dev(x) for x in dl], w, _dev(X0)) for _, dl, w, X0 in insts]
