@@ -216,7 +216,7 @@ struct Variant {
 constexpr Variant kVariants[] = {{4, 8, 1, 1, 1}, {4, 8, 0, 1, 1}, {8, 4, 0, 1, 1},
                                  {8, 8, 0, 1, 1}, {4, 8, 0, 4, 1}, {4, 8, 0, 2, 2}};
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
-constexpr int kDefaultVariant = 3;
+constexpr int kDefaultVariant = 5;
 
 // Tile shape of the in-sample stream: th rows x (64 cpl) columns and the
 // kernel variant.  Order of precedence: FJOFC_TILE ("th:variant"), the
@@ -263,9 +263,17 @@ std::vector<TuneRow> &tune_table() {
 void choose_tiles(int n, int d, int &th, int &variant) {
     th = 256;
     variant = kDefaultVariant;
+    // the rows of d, else those of the nearest tabulated d (the larger one
+    // on a tie): the tile follows n, and a nearby d has a similar register
+    // footprint
+    int dt = -1;
+    for (const TuneRow &r : tune_table()) {
+        const int e = std::abs(r.d - d), et = std::abs(dt - d);
+        if (dt < 0 || e < et || (e == et && r.d > dt)) dt = r.d;
+    }
     int best = -1;
     for (const TuneRow &r : tune_table())
-        if (r.d == d && n <= r.nmax && (best < 0 || r.nmax < best)) {
+        if (r.d == dt && n <= r.nmax && (best < 0 || r.nmax < best)) {
             best = r.nmax;
             th = r.th;
             variant = r.variant;
