@@ -37,7 +37,8 @@
  * Tuning overrides (environment variables, read when a problem is planned
  * or launched; none changes what is computed beyond FP32 summation order):
  *  - FJOFC_TUNE_TABLE  path of the stream tile table (default:
- *                      tune_gfx950.txt next to the library);
+ *                      tune_gfx950.txt next to the library); a d with no
+ *                      rows uses those of the nearest tabulated d;
  *  - FJOFC_TILE        "th:variant" forces the in-sample tile height and
  *                      kernel variant (the height is rounded up to whole
  *                      8-row groups per wavefront);
