@@ -56,7 +56,10 @@ def main(argv=None):
     ap.add_argument("--dims", default="2,3,5")
     ap.add_argument("--m", type=int, default=3)
     ap.add_argument("--out", default=TABLE)
+    ap.add_argument("--buckets", default=None,
+                    help="comma-separated n_max values to tune (default: all)")
     args = ap.parse_args(argv)
+    buckets = BUCKETS if not args.buckets else [int(x) for x in args.buckets.split(",")]
     import numpy as np
     import torch
     from paper_1502_03391_amd import fjofc
@@ -69,7 +72,7 @@ def main(argv=None):
     saved = os.environ.pop("FJOFC_TILE", None)
     try:
         for d in [int(x) for x in args.dims.split(",")]:
-            for nmax in BUCKETS:
+            for nmax in buckets:
                 n = _rep_n(nmax)
                 views, _, X0 = gen.latent_views(1000 + n + d, n, args.m, 8, 0.2, d)
                 delta = [gen.pairwise_dist_torch(Y, dev) for Y in views]
