@@ -115,6 +115,20 @@ def test_one_transform_parity(ctx, monkeypatch, tile, m, n, d):
     assert rg["stress"] == pytest.approx(s1, rel=2e-5)
 
 
+@pytest.mark.parametrize("m,n,d", [(2, 3600, 3), (2, 7000, 5), (2, 14000, 2)])
+def test_one_transform_parity_table_tiles_mid_sizes(ctx, m, n, d):
+    """One transform at mid-size n with the tiles the tuning table picks
+    there (shared 4 x 1 and 2 x 2 wavefront tiles several hundred rows
+    tall), against the oracle."""
+    wmat = _general_wmat(m, seed=n)
+    delta, _, X0 = _problem(500 + d, m, n, d, wmat=wmat)
+    X1o = orc.guttman(delta, wmat, X0)
+    Xg, rg, hg = _gpu_embed(ctx, delta, wmat, X0, 1, want_hist=True)
+    np.testing.assert_allclose(Xg, X1o, rtol=0, atol=2e-5 * np.abs(X1o).max())
+    assert hg[0] == pytest.approx(orc.stress(delta, wmat, X0)[0], rel=2e-6)
+    assert rg["stress"] == pytest.approx(orc.stress(delta, wmat, X1o)[0], rel=2e-5)
+
+
 def test_stress_entry_point(ctx):
     m, n, d = 3, 333, 4
     wmat = _general_wmat(m)
