@@ -47,6 +47,13 @@
  *                      loads even when n % 4 == 0;
  *  - FJOFC_GEMM_WAVES  "1" or "4": wavefronts per workgroup of the network's
  *                      matrix products (default: by product size).
+ * Debug switch:
+ *  - FJOFC_VALIDATE    any value but "0": every in-sample call (fjofc_embed*,
+ *                      fjofc_stress, fjofc_batch_create) first runs
+ *                      fjofc_validate_delta on each Delta_i, and fjofc_oos
+ *                      checks that delta_new is finite and non-negative;
+ *                      an offending entry makes the call return
+ *                      FJOFC_EINVAL (naming the entry) before any other work.
  */
 #ifndef FJOFC_H
 #define FJOFC_H
@@ -303,6 +310,45 @@ int fjofc_mlp_adam(fjofc_mlp *net, float lr, float beta1, float beta2,
 int fjofc_mlp_features(fjofc_ctx *ctx, const float *delta_new, int k, int m,
                        int n, const int *landmarks, int L, const float *mu,
                        const float *inv_sd, unsigned short *x, void *stream);
+
+/* Validation loss: out = network(x), *loss (device FP64) = mean squared
+ * error against y (B x dims[L] FP32).  The parameter gradients are left
+ * as they are.                                                             */
+int fjofc_mlp_loss(fjofc_mlp *net, const unsigned short *x, const float *y, int B,
+                   double *loss, void *stream);
+/* Standardisation statistics of the network's inputs: for an N x F FP32
+ * row-major matrix raw (device), mu[f] = mean of column f and inv_sd[f] =
+ * 1 / max(sd_f, min_sd), sd_f the sample standard deviation (N - 1 in the
+ * denominator; 0 when N = 1).  FP64 sums in a fixed order (two passes), so
+ * results are reproducible.  mu, inv_sd: device F FP32.  Uses the context
+ * workspace ((256 + 1) F doubles); does not synchronise.                  */
+int fjofc_mlp_feature_stats(fjofc_ctx *ctx, const float *raw, int N, int F, double min_sd,
+                            float *mu, float *inv_sd, void *stream);
+/* Consensus point of each new object (the target of a network that
+ * predicts one point for every modality): out[o][c] = (1/m) sum_i
+ * Y[o][i][c], Y device k x m x d FP32 (as for fjofc_oos), out device k x d.
+ */
+int fjofc_oos_consensus(fjofc_ctx *ctx, const float *Y, int k, int m, int d, float *out,
+                        void *stream);
+
+/*
+ * Validation pass over one dissimilarity matrix (a debug check; the
+ * computing calls trust their inputs unless FJOFC_VALIDATE is set).  The
+ * method takes Delta in R_+^{n x n} (Section 1) to be a dissimilarity: every
+ * entry finite and >= 0, Delta symmetric with a zero diagonal.  The stream
+ * reads only the strict upper triangle and the fidelity term of the raw
+ * stress counts each pair once (Remark faststress), so a matrix breaking
+ * these rules would give results that silently depend on the triangle read.
+ *   delta  device n x n FP32 row-major (1 <= n <= 4194240).
+ *   where  optional host: the row-major index i n + j of the first offending
+ *          entry (the smallest such index; an asymmetric pair is reported at
+ *          its upper-triangle entry), -1 when the matrix is valid.
+ * Returns FJOFC_OK, or FJOFC_EINVAL with a message naming (i, j) and the
+ * rule broken (NaN, infinite, negative, asymmetric, non-zero diagonal).
+ * Reads the matrix once through LDS tiles; synchronises `stream`.  Bad
+ * values are only compared, never used in arithmetic that could fault.    */
+int fjofc_validate_delta(fjofc_ctx *ctx, const float *delta, int n, long long *where,
+                         void *stream);
 
 /*
  * Per-kernel timing (tracing aid).  While enabled, every kernel launch of

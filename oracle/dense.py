@@ -189,3 +189,32 @@ def paper_init(delta, d: int):
         blocks.append(xi @ procrustes_rotation(xi, xi0))
         eigs.append(e)
     return np.vstack(blocks), np.array(eigs)
+
+
+# Offence codes of the dissimilarity check (Section 1: Delta in R_+^{n x n},
+# symmetric with a zero diagonal).
+OFFENCES = {1: "nan", 2: "inf", 3: "negative", 4: "asymmetric", 5: "diagonal"}
+
+
+def first_invalid(delta: np.ndarray):
+    """Scan an n x n dissimilarity entry by entry in row-major order and
+    return (index i n + j, offence code) of the first entry that is NaN (1),
+    infinite (2), negative (3), above the diagonal and unequal to its mirror
+    entry (4), or a non-zero diagonal entry (5); (-1, 0) when none is.
+    An entry's own value is judged before the diagonal and symmetry rules."""
+    D = np.asarray(delta, np.float32)
+    n = D.shape[0]
+    for i in range(n):
+        for j in range(n):
+            v = D[i, j]
+            if np.isnan(v):
+                return i * n + j, 1
+            if np.isinf(v):
+                return i * n + j, 2
+            if v < 0:
+                return i * n + j, 3
+            if i == j and v != 0:
+                return i * n + j, 5
+            if i < j and v != D[j, i]:
+                return i * n + j, 4
+    return -1, 0

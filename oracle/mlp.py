@@ -99,6 +99,20 @@ class Adam:
         return out
 
 
+def feature_stats(raw, min_sd: float):
+    """Input standardisation: per-column mean and 1 / max(sample SD, min_sd)
+    (the SD with N - 1 in the denominator), FP64."""
+    r = np.asarray(raw, np.float64)
+    mu = r.mean(axis=0)
+    sd = r.std(axis=0, ddof=1) if r.shape[0] > 1 else np.zeros(r.shape[1])
+    return mu, 1.0 / np.maximum(sd, min_sd)
+
+
+def consensus(Y):
+    """Mean of each object's m points (Y: k x m x d)."""
+    return np.asarray(Y, np.float64).mean(axis=1)
+
+
 def init_params(dims, seed: int) -> Params:
     """He-normal weights (std sqrt(2/fan_in)), zero biases, FP32."""
     rng = np.random.default_rng(seed)

@@ -19,8 +19,8 @@ LIB = os.path.join(HERE, "libfjofc.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["insample.hip", "oos.hip", "cmds.hip", "mlp.hip", "host.cpp", "mlp_host.cpp",
-           "init_host.cpp"]
+SOURCES = ["insample.hip", "oos.hip", "cmds.hip", "mlp.hip", "validate.hip", "host.cpp",
+           "mlp_host.cpp", "init_host.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -204,6 +204,26 @@ hipError_t launch_broadcast(const float *out, int B, int m, int d, int P, float 
 hipError_t launch_features(const float *dnew, int k, int m, int n, const int *lm, int L,
                            const float *mu, const float *isd, uint16_t *x, hipStream_t s);
 
+// Per-feature mean (mu) and 1 / max(sample SD, min_sd) (inv_sd) of an
+// N x F FP32 matrix; scratch: colstats_scratch_doubles(F) doubles.
+hipError_t launch_colstats(const float *raw, long N, int F, double min_sd, float *mu,
+                           float *inv_sd, double *scratch, hipStream_t s);
+size_t colstats_scratch_doubles(int F);
+// out (k x d) = mean over the m points of each object in Y (k x m x d).
+hipError_t launch_consensus(const float *Y, int k, int m, int d, float *out, hipStream_t s);
+
+// ---- input validation (validate.hip) ----------------------------------
+// Smallest ((row-major index) << 3 | offence) over the offending entries
+// of an n x n dissimilarity matrix (offences: 1 NaN, 2 infinite, 3
+// negative, 4 asymmetric (reported at the upper-triangle entry), 5 non-zero
+// diagonal), atomically min-ed into *first (~0 when none; `reset` sets it
+// to ~0 first).
+hipError_t launch_validate_square(const float *delta, int n, unsigned long long *first,
+                                  bool reset, hipStream_t s);
+// The same over `count` consecutive dissimilarities (offences 1-3 only).
+hipError_t launch_validate_rows(const float *d, long long count, unsigned long long *first,
+                                bool reset, hipStream_t s);
+
 // Records the calling thread's error message (host.cpp); returns `code`.
 int set_error(int code, const char *fmt, ...);
 // Context services for entry points outside host.cpp: its device, its

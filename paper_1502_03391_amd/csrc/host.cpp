@@ -12,6 +12,7 @@
 #include <cstdlib>
 #include <dlfcn.h>
 #include <array>
+#include <functional>
 #include <map>
 #include <tuple>
 #include <string>
@@ -25,6 +26,8 @@ struct fjofc_ctx {
     size_t ws_bytes = 0;
     void *pinned = nullptr;      // small pinned host staging buffer
     size_t pinned_bytes = 0;
+    unsigned long long *vslot = nullptr;  // device result of the validation pass
+    hipEvent_t chunk_ev[2] = {nullptr, nullptr};  // chunked enqueue of stopping runs
     // profiling: (kind, start, stop, bytes) per timed launch
     bool prof = false;
     struct Rec {
@@ -312,6 +315,73 @@ int check_problem(const float *const *delta, int m, int n, int d, const void *X)
     return FJOFC_OK;
 }
 
+// ---- optional validation of the dissimilarities ------------------------
+// FJOFC_VALIDATE (any value but "0") runs the pass before every in-sample,
+// batched and out-of-sample call.
+bool validate_on() {
+    const char *e = std::getenv("FJOFC_VALIDATE");
+    return e && e[0] && !(e[0] == '0' && e[1] == 0);
+}
+
+const char *offence_name(int k) {
+    switch (k) {
+    case 1: return "is NaN";
+    case 2: return "is infinite";
+    case 3: return "is negative";
+    case 4: return "differs from its mirror entry (Delta must be symmetric)";
+    case 5: return "is a non-zero diagonal entry";
+    default: return "is invalid";
+    }
+}
+
+// Reads the validation slot (synchronises s); *code = ~0 when clean.
+int read_vslot(fjofc_ctx *c, hipStream_t s, unsigned long long *code) {
+    int rc = ensure_pinned(c, 256);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(c->pinned, c->vslot, sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    std::memcpy(code, c->pinned, sizeof *code);
+    return FJOFC_OK;
+}
+
+int ensure_vslot(fjofc_ctx *c) {
+    if (c->vslot) return FJOFC_OK;
+    if (hipMalloc(reinterpret_cast<void **>(&c->vslot), 256) != hipSuccess) {
+        c->vslot = nullptr;
+        return fail(FJOFC_ENOMEM, "validation slot allocation failed");
+    }
+    return FJOFC_OK;
+}
+
+// Checks one n x n matrix; `label` names it in the message.  *where (optional)
+// receives the row-major index of the first offending entry, or -1.
+int validate_square(fjofc_ctx *c, const float *delta, int n, const char *label,
+                    long long *where, hipStream_t s) {
+    if (where) *where = -1;
+    int rc = ensure_vslot(c);
+    if (rc) return rc;
+    HIP_TRY(launch_validate_square(delta, n, c->vslot, true, s));
+    unsigned long long code = 0;
+    rc = read_vslot(c, s, &code);
+    if (rc) return rc;
+    if (code == ~0ull) return FJOFC_OK;
+    const long long idx = (long long)(code >> 3);
+    if (where) *where = idx;
+    return fail(FJOFC_EINVAL, "%s: entry (%lld, %lld) %s", label, idx / n, idx % n,
+                offence_name((int)(code & 7)));
+}
+
+int validate_problem(fjofc_ctx *c, const float *const *delta, int m, int n, hipStream_t s) {
+    for (int i = 0; i < m; ++i) {
+        char label[32];
+        std::snprintf(label, sizeof label, "Delta_%d", i);
+        const int rc = validate_square(c, delta[i], n, label, nullptr, s);
+        if (rc) return rc;
+    }
+    return FJOFC_OK;
+}
+
 // Host-side plan of one in-sample problem: geometry, tile list, W^-1.
 struct HostInst {
     TriGeom g{};
@@ -483,13 +553,26 @@ struct Fork {
     std::vector<hipEvent_t> join;
 };
 
+// Transforms per enqueued chunk of a run that can stop early (eager runs
+// with a stop rule): after every chunk the host reads the device's done
+// flag of the chunk before, so at most one chunk is enqueued past a stop.
+constexpr int kChunk = 32;
+
+// Called after the transforms [0, p) are enqueued (p a multiple of kChunk,
+// p < iters); sets `stop` when no more transforms need enqueueing.
+using ChunkHook = std::function<int(int p, bool &stop)>;
+
 // Enqueue Algorithm 2's loop for instances advancing in lockstep.  Used
 // eagerly by fjofc_embed and under stream capture by the batched plan
 // (which passes `fork` so that its groups become parallel graph branches).
+// With `hook`, the loop asks after every kChunk transforms whether to go
+// on; the closing stress pass and copy-out are enqueued in any case (they
+// are no-ops for stopped instances).
 int enqueue_loop(fjofc_ctx *ctx, const InstDesc *insts, int count, int maxm,
                  const std::vector<StreamGroup> &groups, const RowItem *rows, int nrows,
                  int iters, double tol, int tol_mode, int stress_every, int nhist,
-                 bool stress_only, hipStream_t s, const Fork *fork = nullptr) {
+                 bool stress_only, hipStream_t s, const Fork *fork = nullptr,
+                 const ChunkHook *hook = nullptr) {
     HIP_TRY(launch_init(insts, count, nhist, s));
     HIP_TRY(launch_com(insts, rows, nrows, s));
     const bool forked = fork && groups.size() > 1 && fork->side.size() + 1 >= groups.size();
@@ -532,8 +615,16 @@ int enqueue_loop(fjofc_ctx *ctx, const InstDesc *insts, int count, int maxm,
             Timed tm(ctx, K_RED, 0.0, s);
             HIP_TRY(launch_reduce(insts, count, p, 1, 0, iters, tol, tol_mode, s));
         }
-        Timed tm(ctx, K_FIN, 0.0, s);
-        HIP_TRY(launch_finalize(maxm, insts, rows, nrows, p & 1, next_due, s));
+        {
+            Timed tm(ctx, K_FIN, 0.0, s);
+            HIP_TRY(launch_finalize(maxm, insts, rows, nrows, p & 1, next_due, s));
+        }
+        if (hook && (p + 1) % kChunk == 0 && p + 1 < iters) {
+            bool stop = false;
+            rc = (*hook)(p + 1, stop);
+            if (rc) return rc;
+            if (stop) break;
+        }
     }
     // stress of the returned configuration (and the checkpoint test at
     // t = iters) unless the stop rule already fired.
@@ -562,6 +653,7 @@ int run_insample(fjofc_ctx *ctx, const float *const *delta, int m, int n,
     HostInst h;
     rc = plan_instance(delta, m, n, wmat, d, X, iters + 1, h);
     if (rc) return rc;
+    if (validate_on() && (rc = validate_problem(ctx, delta, m, n, s))) return rc;
     h.alpha = alpha;
     std::vector<StreamItem> items;
     std::vector<RowItem> rows;
@@ -596,11 +688,31 @@ int run_insample(fjofc_ctx *ctx, const float *const *delta, int m, int n,
     const double bytes = 4.0 * m * 0.5 * n * (n - 1.0);
     std::vector<StreamGroup> groups{{d, h.g.variant, h.g.vec4, d_items, (int)items.size(), bytes,
                                      stream_lds(h.g, d), d_rows, (int)rows.size(), m}};
+    char *pin = static_cast<char *>(ctx->pinned);
+    // A run that can stop early is enqueued chunk by chunk: after chunk c
+    // the done flag is copied to pinned slot c % 2, and before enqueueing
+    // chunk c + 1 the host reads the flag of chunk c - 1, so one chunk is
+    // always queued ahead of the check.
+    const bool can_stop = tol > 0.0 && tol_mode != FJOFC_TOL_NONE && iters > kChunk;
+    int *flag[2] = {reinterpret_cast<int *>(pin + 128), reinterpret_cast<int *>(pin + 192)};
+    ChunkHook hook = [&](int p, bool &stop) -> int {
+        const int c = p / kChunk - 1;  // the chunk just enqueued
+        HIP_TRY(hipMemcpyAsync(flag[c & 1], &desc.st->done, sizeof(int), hipMemcpyDeviceToHost,
+                               s));
+        HIP_TRY(hipEventRecord(ctx->chunk_ev[c & 1], s));
+        if (c >= 1) {
+            HIP_TRY(hipEventSynchronize(ctx->chunk_ev[(c - 1) & 1]));
+            stop = *flag[(c - 1) & 1] != 0;
+        }
+        return FJOFC_OK;
+    };
+    if (can_stop)
+        for (hipEvent_t &e : ctx->chunk_ev)
+            if (!e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     rc = enqueue_loop(ctx, d_desc, 1, m, groups, d_rows, (int)rows.size(), iters, tol, tol_mode,
-                      stress_every, iters + 1, stress_only, s);
+                      stress_every, iters + 1, stress_only, s, nullptr, can_stop ? &hook : nullptr);
     if (rc) return rc;
 
-    char *pin = static_cast<char *>(ctx->pinned);
     HIP_TRY(hipMemcpyAsync(pin, desc.st, sizeof(EmbedState), hipMemcpyDeviceToHost, s));
     if (stress_hist)
         HIP_TRY(hipMemcpyAsync(pin + 256, desc.hist, sizeof(double) * (iters + 1),
@@ -716,6 +828,9 @@ void fjofc_destroy(fjofc_ctx *c) {
     (void)hipDeviceSynchronize();
     if (c->ws) (void)hipFree(c->ws);
     if (c->pinned) (void)hipHostFree(c->pinned);
+    if (c->vslot) (void)hipFree(c->vslot);
+    for (hipEvent_t e : c->chunk_ev)
+        if (e) (void)hipEventDestroy(e);
     for (auto &r : c->recs) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
@@ -781,6 +896,19 @@ int fjofc_oos(fjofc_ctx *ctx, const float *X_in, int m, int n, int d,
     if (rc) return rc;
     DeviceGuard dg(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (validate_on() && k > 0) {
+        rc = ensure_vslot(ctx);
+        if (rc) return rc;
+        HIP_TRY(launch_validate_rows(delta_new, (long long)k * m * n, ctx->vslot, true, s));
+        unsigned long long code = 0;
+        rc = read_vslot(ctx, s, &code);
+        if (rc) return rc;
+        if (code != ~0ull) {
+            const long long idx = (long long)(code >> 3), row = idx / n;
+            return fail(FJOFC_EINVAL, "delta_new: object %lld, modality %lld, entry %lld %s",
+                        row / m, row % m, idx % n, offence_name((int)(code & 7)));
+        }
+    }
 
     std::vector<double> W((size_t)m * m), Li((size_t)m * m);
     wmod(m, n, wmat, W.data());
@@ -847,6 +975,16 @@ int fjofc_oos_nearest_start(fjofc_ctx *ctx, const float *X_in, int m, int n, int
     return FJOFC_OK;
 }
 
+int fjofc_validate_delta(fjofc_ctx *ctx, const float *delta, int n, long long *where,
+                         void *stream) {
+    if (where) *where = -1;
+    if (!ctx) return fail(FJOFC_EINVAL, "ctx is NULL");
+    if (n < 1 || n > 65535 * 64) return fail(FJOFC_EINVAL, "n=%d out of range", n);
+    if (!delta) return fail(FJOFC_EINVAL, "delta is NULL");
+    DeviceGuard dg(ctx->device);
+    return validate_square(ctx, delta, n, "Delta", where, static_cast<hipStream_t>(stream));
+}
+
 int fjofc_profile_enable(fjofc_ctx *ctx, int on) {
     if (!ctx) return fail(FJOFC_EINVAL, "ctx is NULL");
     DeviceGuard dg(ctx->device);
@@ -903,7 +1041,8 @@ int fjofc_batch_create(fjofc_ctx *ctx, const fjofc_problem *probs, int count,
     b->hi.resize(count);
     for (int p = 0; p < count; ++p) {
         const fjofc_problem &q = probs[p];
-        const int rc = plan_instance(q.delta, q.m, q.n, q.wmat, q.d, q.X, 0, b->hi[p]);
+        int rc = plan_instance(q.delta, q.m, q.n, q.wmat, q.d, q.X, 0, b->hi[p]);
+        if (!rc && validate_on()) rc = validate_problem(ctx, q.delta, q.m, q.n, nullptr);
         if (rc) {
             batch_free(b);
             return fail(rc, "problem %d: %s", p, g_err.c_str());

@@ -622,7 +622,12 @@ __global__ __launch_bounds__(RED_BLOCK) void reduce_kernel(
 }
 
 // Per instance: reset the loop state, fill the history with NaN, convert X0
-// to SoA (padding rows 0).  One workgroup per instance.
+// to SoA (padding rows 0) and zero the other buffer.  The finalize writes
+// X_{t+1} only on rows below npad / FIN_ROWS * FIN_ROWS; when npad is not a
+// multiple of FIN_ROWS (a tile height above the tile width) boundary tiles
+// still read the rows above, with their terms masked to r = 0, so those
+// rows must hold finite values (0) in both buffers.  One workgroup per
+// instance.
 __global__ void init_kernel(const InstDesc *__restrict__ insts, int nhist) {
     const InstDesc &b = insts[blockIdx.x];
     const TriGeom &g = b.g;
@@ -641,9 +646,11 @@ __global__ void init_kernel(const InstDesc *__restrict__ insts, int nhist) {
     const int tot = g.m * g.npad;
     for (int q = threadIdx.x; q < tot; q += blockDim.x) {
         const int a = q / g.npad, j = q - a * g.npad;
-        for (int k = 0; k < D; ++k)
+        for (int k = 0; k < D; ++k) {
             b.Xs[0][((size_t)a * D + k) * g.npad + j] =
                 (j < g.n) ? b.X[((size_t)a * g.n + j) * D + k] : 0.f;
+            b.Xs[1][((size_t)a * D + k) * g.npad + j] = 0.f;
+        }
     }
 }
 

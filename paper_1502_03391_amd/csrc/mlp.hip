@@ -317,6 +317,69 @@ __global__ void broadcast_kernel(const float *__restrict__ out, int B, int m, in
     }
 }
 
+// Per-feature statistics of an N x F FP32 matrix (row-major), for the
+// standardisation of the network's inputs.  Pass 0: slice partials of the
+// column sums; pass 1: slice partials of the squared deviations from the
+// FP64 mean.  Slice s takes rows s, s + STAT_SLICES, ...; consecutive threads
+// read consecutive features of a row.  All sums FP64, fixed order.
+constexpr int STAT_SLICES = 256;
+template <int PASS>
+__global__ __launch_bounds__(256) void colstats_part_kernel(const float *__restrict__ raw,
+                                                            long N, int F,
+                                                            const double *__restrict__ mean,
+                                                            double *__restrict__ part) {
+    const int f = blockIdx.x * 256 + threadIdx.x;
+    if (f >= F) return;
+    const double c = PASS == 0 ? 0.0 : mean[f];
+    double a0 = 0.0, a1 = 0.0;
+    long r = blockIdx.y;
+    for (; r + STAT_SLICES < N; r += 2 * STAT_SLICES) {
+        const double x0 = (double)raw[r * F + f] - c;
+        const double x1 = (double)raw[(r + STAT_SLICES) * F + f] - c;
+        a0 += PASS == 0 ? x0 : x0 * x0;
+        a1 += PASS == 0 ? x1 : x1 * x1;
+    }
+    if (r < N) {
+        const double x0 = (double)raw[r * F + f] - c;
+        a0 += PASS == 0 ? x0 : x0 * x0;
+    }
+    part[(long)blockIdx.y * F + f] = a0 + a1;
+}
+
+// Pass 0: mean[f] = sum / N (FP64) and mu[f] = FP32 mean.  Pass 1:
+// inv_sd[f] = 1 / max(sqrt(sum / (N - 1)), min_sd) (N = 1: 1 / min_sd).
+template <int PASS>
+__global__ void colstats_finish_kernel(const double *__restrict__ part, long N, int F,
+                                       double min_sd, double *__restrict__ mean,
+                                       float *__restrict__ out) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= F) return;
+    double t = 0.0;
+    for (int q = 0; q < STAT_SLICES; ++q) t += part[(long)q * F + f];
+    if (PASS == 0) {
+        mean[f] = t / (double)N;
+        out[f] = (float)(t / (double)N);
+    } else {
+        const double sd = N > 1 ? sqrt(t / (double)(N - 1)) : 0.0;
+        out[f] = (float)(1.0 / fmax(sd, min_sd));
+    }
+}
+
+// Consensus point of each new object: out[o][c] = (1/m) sum_i Y[o][i][c]
+// (FP64 sum in modality order).
+__global__ void consensus_kernel(const float *__restrict__ Y, int k, int m, int d,
+                                 float *__restrict__ out) {
+    const long tot = (long)k * d;
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < tot;
+         q += (long)gridDim.x * blockDim.x) {
+        const long o = q / d;
+        const int c = (int)(q - o * d);
+        double t = 0.0;
+        for (int i = 0; i < m; ++i) t += (double)Y[(o * m + i) * d + c];
+        out[q] = (float)(t / m);
+    }
+}
+
 }  // namespace
 
 hipError_t launch_broadcast(const float *out, int B, int m, int d, int P, float *Y,
@@ -422,6 +485,28 @@ hipError_t launch_features(const float *dnew, int k, int m, int n, const int *lm
     const long tot = (long)k * m * L;
     const unsigned nb = (unsigned)std::min<long>(8192, (tot + 255) / 256);
     features_kernel<<<nb > 0 ? nb : 1, 256, 0, s>>>(dnew, k, m, n, lm, L, mu, isd, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_colstats(const float *raw, long N, int F, double min_sd, float *mu,
+                           float *inv_sd, double *scratch, hipStream_t s) {
+    // scratch: STAT_SLICES * F partials, then F FP64 means
+    double *part = scratch, *mean = scratch + (long)STAT_SLICES * F;
+    const dim3 grid((unsigned)((F + 255) / 256), STAT_SLICES);
+    const unsigned nf = (unsigned)((F + 255) / 256);
+    colstats_part_kernel<0><<<grid, 256, 0, s>>>(raw, N, F, mean, part);
+    colstats_finish_kernel<0><<<nf, 256, 0, s>>>(part, N, F, min_sd, mean, mu);
+    colstats_part_kernel<1><<<grid, 256, 0, s>>>(raw, N, F, mean, part);
+    colstats_finish_kernel<1><<<nf, 256, 0, s>>>(part, N, F, min_sd, mean, inv_sd);
+    return hipGetLastError();
+}
+
+size_t colstats_scratch_doubles(int F) { return (size_t)(STAT_SLICES + 1) * F; }
+
+hipError_t launch_consensus(const float *Y, int k, int m, int d, float *out, hipStream_t s) {
+    const long tot = (long)k * d;
+    const unsigned nb = (unsigned)std::min<long>(4096, (tot + 255) / 256);
+    consensus_kernel<<<nb > 0 ? nb : 1, 256, 0, s>>>(Y, k, m, d, out);
     return hipGetLastError();
 }
 

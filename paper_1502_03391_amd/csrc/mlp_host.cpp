@@ -338,4 +338,47 @@ int fjofc_mlp_features(fjofc_ctx *ctx, const float *delta_new, int k, int m, int
     return FJOFC_OK;
 }
 
+int fjofc_mlp_loss(fjofc_mlp *n, const unsigned short *x, const float *y, int B, double *loss,
+                   void *stream) {
+    int rc = check_batch(n, B);
+    if (rc) return rc;
+    if (!x || !y || !loss) return set_error(FJOFC_EINVAL, "NULL argument");
+    Dev dg(n->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rc = forward(n, x, B, s);
+    if (rc) return rc;
+    // the output gradient lands in the network's own scratch buffers; the
+    // parameter gradients are untouched
+    HIP_CHECK(launch_mse(n->out, y, B, n->dims[n->L], n->Gf[0], n->Gb[0], n->GbT[0], n->ldt,
+                         loss, n->scratch, s));
+    return FJOFC_OK;
+}
+
+int fjofc_mlp_feature_stats(fjofc_ctx *ctx, const float *raw, int N, int F, double min_sd,
+                            float *mu, float *inv_sd, void *stream) {
+    if (!ctx) return set_error(FJOFC_EINVAL, "ctx is NULL");
+    if (N < 1 || F < 1) return set_error(FJOFC_EINVAL, "bad sizes N=%d F=%d", N, F);
+    if (!raw || !mu || !inv_sd) return set_error(FJOFC_EINVAL, "NULL argument");
+    if (!(min_sd > 0.0) || !std::isfinite(min_sd))
+        return set_error(FJOFC_EINVAL, "min_sd must be finite and > 0");
+    Dev dg(ctx_device(ctx));
+    void *ws = nullptr;
+    int rc = ctx_workspace(ctx, sizeof(double) * colstats_scratch_doubles(F), &ws);
+    if (rc) return rc;
+    HIP_CHECK(launch_colstats(raw, N, F, min_sd, mu, inv_sd, static_cast<double *>(ws),
+                              static_cast<hipStream_t>(stream)));
+    return FJOFC_OK;
+}
+
+int fjofc_oos_consensus(fjofc_ctx *ctx, const float *Y, int k, int m, int d, float *out,
+                        void *stream) {
+    if (!ctx) return set_error(FJOFC_EINVAL, "ctx is NULL");
+    if (k < 0 || m < 1 || d < 1) return set_error(FJOFC_EINVAL, "bad sizes");
+    if (k == 0) return FJOFC_OK;
+    if (!Y || !out) return set_error(FJOFC_EINVAL, "NULL argument");
+    Dev dg(ctx_device(ctx));
+    HIP_CHECK(launch_consensus(Y, k, m, d, out, static_cast<hipStream_t>(stream)));
+    return FJOFC_OK;
+}
+
 }  // extern "C"

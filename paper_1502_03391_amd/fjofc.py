@@ -29,7 +29,8 @@ EXPORTS = ["fjofc_create", "fjofc_destroy", "fjofc_last_error", "fjofc_strerror"
            "fjofc_mlp_get_params", "fjofc_mlp_forward", "fjofc_mlp_backward",
            "fjofc_mlp_get_grads", "fjofc_mlp_adam", "fjofc_mlp_features",
            "fjofc_mlp_predict_start", "fjofc_oos_nearest_start", "fjofc_embed_relaxed",
-           "fjofc_init_cmds"]
+           "fjofc_init_cmds", "fjofc_mlp_loss", "fjofc_mlp_feature_stats",
+           "fjofc_oos_consensus", "fjofc_validate_delta"]
 
 
 class FjofcResult(C.Structure):
@@ -120,6 +121,10 @@ def lib():
         L.fjofc_mlp_get_grads.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), vp]
         L.fjofc_mlp_adam.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float, vp]
         L.fjofc_mlp_features.argtypes = [vp, vp, ip, ip, ip, vp, ip, vp, vp, vp, vp]
+        L.fjofc_mlp_loss.argtypes = [vp, vp, vp, ip, vp, vp]
+        L.fjofc_mlp_feature_stats.argtypes = [vp, vp, ip, ip, dp, vp, vp, vp]
+        L.fjofc_oos_consensus.argtypes = [vp, vp, ip, ip, ip, vp, vp]
+        L.fjofc_validate_delta.argtypes = [vp, vp, ip, C.POINTER(C.c_longlong), vp]
         L.fjofc_profile_enable.argtypes = [vp, ip]
         L.fjofc_profile_read.argtypes = [vp, C.POINTER(FjofcProfile)]
         _lib = L
@@ -412,6 +417,15 @@ class Mlp:
                                          self._ptrs(db, torch.float32, "db"), _stream_ptr(stream)))
         return dW, db
 
+    def loss(self, x, y, loss, stream=None):
+        """loss (device FP64, 1 element) = mean squared error of network(x)
+        against y; gradients untouched."""
+        import torch
+        _check(lib().fjofc_mlp_loss(self._h, _dev_ptr(x, torch.bfloat16, "x"),
+                                    _dev_ptr(y, torch.float32, "y"), int(x.shape[0]),
+                                    _dev_ptr(loss, torch.float64, "loss"), _stream_ptr(stream)))
+        return loss
+
     def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
         _check(lib().fjofc_mlp_adam(self._h, float(lr), float(beta1), float(beta2), float(eps),
                                     _stream_ptr(stream)))
@@ -442,3 +456,44 @@ def fjofc_mlp_features(ctx: Context, delta_new, landmarks, mu, inv_sd, x, stream
                                     _dev_ptr(inv_sd, torch.float32, "inv_sd"),
                                     _dev_ptr(x, torch.bfloat16, "x"), _stream_ptr(stream)))
     return x
+
+
+def fjofc_mlp_feature_stats(ctx: Context, raw, mu, inv_sd, min_sd: float = 1e-6, stream=None):
+    """mu, inv_sd (F FP32) = column means and 1 / max(sample SD, min_sd) of
+    raw (N x F FP32)."""
+    import torch
+    N, F = (int(s) for s in raw.shape)
+    _check(lib().fjofc_mlp_feature_stats(ctx.handle, _dev_ptr(raw, torch.float32, "raw"), N, F,
+                                         float(min_sd), _dev_ptr(mu, torch.float32, "mu"),
+                                         _dev_ptr(inv_sd, torch.float32, "inv_sd"),
+                                         _stream_ptr(stream)))
+    return mu, inv_sd
+
+
+def fjofc_oos_consensus(ctx: Context, Y, out, stream=None):
+    """out (k x d) = mean over the m modality points of each object in Y
+    (k x m x d)."""
+    import torch
+    k, m, d = (int(s) for s in Y.shape)
+    _check(lib().fjofc_oos_consensus(ctx.handle, _dev_ptr(Y, torch.float32, "Y"), k, m, d,
+                                     _dev_ptr(out, torch.float32, "out"), _stream_ptr(stream)))
+    return out
+
+
+def fjofc_validate_delta(ctx: Context, delta, stream=None) -> int:
+    """Check one n x n dissimilarity matrix (finite, >= 0, symmetric, zero
+    diagonal).  Returns -1 when valid; raises FjofcError (code 1) naming the
+    first offending entry otherwise (its row-major index is in .where)."""
+    import torch
+    n = int(delta.shape[0])
+    if delta.dim() != 2 or int(delta.shape[1]) != n:
+        raise ValueError("delta must be n x n")
+    where = C.c_longlong(-1)
+    rc = lib().fjofc_validate_delta(ctx.handle, _dev_ptr(delta, torch.float32, "delta"), n,
+                                    C.byref(where), _stream_ptr(stream))
+    if rc != FJOFC_OK:
+        err = FjofcError(rc, lib().fjofc_last_error().decode())
+        err.where = int(where.value)
+        raise err
+    return int(where.value)
+

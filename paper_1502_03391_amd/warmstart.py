@@ -8,17 +8,21 @@ device memory and does index plumbing):
    dissimilarities to all in-sample objects; out-of-sample transforms from
    the nearest-in-sample start run until the stress stops decreasing
    (fjofc_oos_nearest_start, fjofc_oos with a tolerance).  The target is the
-   converged point of every modality (m d outputs), or their mean with
-   `per_modality` off.
+   converged point of every modality (m d outputs, `per_modality`), or the
+   consensus point, their mean over the modalities (fjofc_oos_consensus; d
+   outputs, every modality then starts from it).
 3. Features: the dissimilarities to L fixed landmark objects in every
-   modality, standardised with training statistics (fjofc_mlp_features).
-4. Training: MSE, Adam, cosine learning rate (fjofc_mlp_backward / _adam).
+   modality, standardised with training statistics (fjofc_mlp_feature_stats,
+   fjofc_mlp_features).
+4. Training: MSE, Adam, cosine learning rate (fjofc_mlp_backward / _adam);
+   validation loss by fjofc_mlp_loss.
 5. Evaluation on held-out objects: the plain random start runs `oos_iters`
-   transforms and defines each object's reference stress; the learned start
-   (features + network, fjofc_mlp_predict_start) and the nearest-in-sample
-   start run until their stress is within `rel` of the reference
-   (fjofc_oos target, same iteration cap).  Iterations per object and the
-   wall time of each whole start-plus-refine pipeline are reported.
+   transforms and defines each object's reference stress.  Then, each until
+   its stress is within `rel` of the reference (fjofc_oos target, the same
+   iteration cap): the same plain start again, the learned start (features +
+   network, fjofc_mlp_predict_start) and the nearest-in-sample start.  Every
+   pipeline runs in calls of `oos_batch` objects.  Iterations per object and
+   the wall time of each whole start-plus-refine pipeline are reported.
 """
 from __future__ import annotations
 
@@ -43,10 +47,10 @@ class WarmStartConfig:
     batch: int = 1024
     lr: float = 1e-3
     oos_iters: int = 100
-    oos_batch: int = 4096     # objects per fjofc_oos call in the plain reference run
+    oos_batch: int = 4096     # objects per fjofc_oos call (and network call), every pipeline
     chunk: int = 20000        # training objects generated per chunk
     rel: float = 1e-4
-    per_modality: bool = True
+    per_modality: bool = True  # False: one consensus point (d outputs)
     target_iters: int = 300   # cap of the transforms that make training targets
     target_tol: float = 1e-7  # ... stopped when the stress decreases by less
     seed_landmarks: int = 22
@@ -105,36 +109,46 @@ def _run_oos(ctx, prob, dnew, Y, iters, batch, target=None, stress=None, its=Non
 
 
 def training_data(ctx, prob, cfg: WarmStartConfig, landmarks, log=print):
-    """Features (raw, FP32 for the statistics) and targets of the training
-    objects, generated chunk by chunk."""
+    """Raw landmark features (FP32, for the statistics) and the converged
+    out-of-sample points (N x m x d) of the training objects, generated
+    chunk by chunk."""
     import torch
     from workloads import generators as gen
     sp = prob.spec
     new = gen.oos_objects(cfg.seed_train, cfg.train_objects, prob.maps, sp.sigma)
-    out_dim = sp.m * sp.d if cfg.per_modality else sp.d
     raw = torch.empty((cfg.train_objects, sp.m * cfg.landmarks), dtype=torch.float32,
                       device=prob.device)
-    tgt = torch.empty((cfg.train_objects, out_dim), dtype=torch.float32, device=prob.device)
+    Yt = torch.empty((cfg.train_objects, sp.m, sp.d), dtype=torch.float32, device=prob.device)
     buf = None
     lm = landmarks.long()
     its_all = []
     for o0 in range(0, cfg.train_objects, cfg.chunk):
         o1 = min(cfg.train_objects, o0 + cfg.chunk)
         buf = prob.new_delta(new, o0, o1, None if buf is None or buf.shape[0] != o1 - o0 else buf)
-        Y = torch.empty((o1 - o0, sp.m, sp.d), dtype=torch.float32, device=prob.device)
+        Y = Yt[o0:o1]
         fjofc.fjofc_oos_nearest_start(ctx, prob.X, buf, Y)
         its = torch.empty(o1 - o0, dtype=torch.int32, device=prob.device)
         fjofc.fjofc_oos(ctx, prob.X, prob.wmat, buf, Y, cfg.target_iters, tol=cfg.target_tol,
                         iters_out=its, sync=False)
         raw[o0:o1] = buf[:, :, lm].reshape(o1 - o0, -1)
-        tgt[o0:o1] = Y.reshape(o1 - o0, -1) if cfg.per_modality else Y.mean(dim=1)
         its_all.append(its)
         log(f"[warmstart] training data {o1}/{cfg.train_objects}")
     torch.cuda.synchronize()
     its = torch.cat(its_all).float()
     log(f"[warmstart] target transforms: mean {float(its.mean()):.1f}, "
         f"capped {float((its >= cfg.target_iters).float().mean()):.3f}")
-    return raw, tgt
+    return raw, Yt
+
+
+def targets(ctx, Yt, per_modality: bool):
+    """Network targets from the converged points: every modality's point
+    (N x m d) or the consensus point (N x d)."""
+    import torch
+    N, m, d = Yt.shape
+    if per_modality:
+        return Yt.reshape(N, m * d)
+    out = torch.empty((N, d), dtype=torch.float32, device=Yt.device)
+    return fjofc.fjofc_oos_consensus(ctx, Yt, out)
 
 
 def train_network(ctx, raw, tgt, cfg: WarmStartConfig, log=print):
@@ -142,8 +156,9 @@ def train_network(ctx, raw, tgt, cfg: WarmStartConfig, log=print):
     learning rate.  Returns (net, mu, inv_sd, history)."""
     import torch
     N = raw.shape[0]
-    mu = raw.mean(0)
-    inv_sd = 1.0 / raw.std(0).clamp_min(1e-6)
+    mu = torch.empty(raw.shape[1], dtype=torch.float32, device=raw.device)
+    inv_sd = torch.empty_like(mu)
+    fjofc.fjofc_mlp_feature_stats(ctx, raw, mu, inv_sd, min_sd=1e-6)
     dims = [raw.shape[1]] + [cfg.hidden] * cfg.depth + [tgt.shape[1]]
     rng = np.random.default_rng(cfg.seed_init)
     W = [torch.from_numpy((rng.standard_normal((a, b)) * math.sqrt(2.0 / a)).astype(np.float32))
@@ -155,8 +170,7 @@ def train_network(ctx, raw, tgt, cfg: WarmStartConfig, log=print):
     m = raw.shape[1] // cfg.landmarks
     xs = torch.empty(raw.shape, dtype=torch.bfloat16, device=raw.device)
     ident = torch.arange(cfg.landmarks, dtype=torch.int32, device=raw.device)
-    fjofc.fjofc_mlp_features(ctx, raw.view(N, m, cfg.landmarks), ident, mu.contiguous(),
-                             inv_sd.contiguous(), xs)
+    fjofc.fjofc_mlp_features(ctx, raw.view(N, m, cfg.landmarks), ident, mu, inv_sd, xs)
     perm0 = torch.from_numpy(rng.permutation(N)).to(raw.device)
     nval = int(N * cfg.val_frac)
     val_idx, tr_idx = perm0[:nval], perm0[nval:]
@@ -184,73 +198,62 @@ def train_network(ctx, raw, tgt, cfg: WarmStartConfig, log=print):
 
 
 def evaluate_loss(net, x, y, batch):
+    """Mean squared error over x (library forward and MSE kernels)."""
     import torch
     tot = 0.0
-    out = torch.empty((batch, y.shape[1]), dtype=torch.float32, device=x.device)
+    loss = torch.zeros(1, dtype=torch.float64, device=x.device)
     for o0 in range(0, x.shape[0], batch):
         o1 = min(x.shape[0], o0 + batch)
-        o = net.forward(x[o0:o1], out[: o1 - o0])
-        tot += float(((o - y[o0:o1]) ** 2).sum())
-    return tot / (x.shape[0] * y.shape[1])
+        net.loss(x[o0:o1], y[o0:o1], loss)
+        tot += float(loss.item()) * (o1 - o0)
+    return tot / x.shape[0]
 
 
-def evaluate(ctx, prob, net, mu, inv_sd, landmarks, cfg: WarmStartConfig, k: int = 50000,
-             log=print):
-    """Plain start (reference), learned warm start and nearest-in-sample start
-    on k held-out objects: transforms and wall time to reach the plain
-    start's final stress within `rel`."""
+def evaluate(ctx, prob, nets, landmarks, cfg: WarmStartConfig, k: int = 50000, log=print):
+    """On k held-out objects: the plain start's reference run, then the time
+    and transforms each start needs to reach that reference stress within
+    `rel` (the same start, every learned start in `nets`, the
+    nearest-in-sample start).  `nets` maps a name to (net, mu, inv_sd).
+    Every pipeline runs in calls of cfg.oos_batch objects."""
     import torch
     from workloads import generators as gen
     sp = prob.spec
     dev = prob.device
+    nb = cfg.oos_batch
     new = gen.oos_objects(cfg.seed_eval, k, prob.maps, sp.sigma)
     dnew = prob.new_delta(new, 0, k)
     Y0 = prob.plain_start(cfg.seed_start, k)
     torch.cuda.synchronize()
 
-    # plain start: the reference run, in calls of oos_batch objects
+    # plain start: the reference run (oos_iters transforms, no stop rule)
     Yp = Y0.clone()
     sp_stress = torch.empty(k, dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _run_oos(ctx, prob, dnew, Yp, cfg.oos_iters, cfg.oos_batch, stress=sp_stress)
+    _run_oos(ctx, prob, dnew, Yp, cfg.oos_iters, nb, stress=sp_stress)
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
     target = sp_stress * (1.0 + cfg.rel)
 
-    def refine(Ystart):
+    def refine(Ystart, o0, o1, st, it):
+        fjofc.fjofc_oos(ctx, prob.X, prob.wmat, dnew[o0:o1], Ystart[o0:o1], cfg.oos_iters,
+                        target=target[o0:o1], stress_out=st[o0:o1], iters_out=it[o0:o1],
+                        sync=False)
+
+    def timed(start_fn):
+        """start_fn(o0, o1, Y) writes the start of objects o0..o1-1 into Y;
+        the pipeline (start + refine) runs call by call and is timed whole."""
+        Y = torch.empty((k, sp.m, sp.d), dtype=torch.float32, device=dev)
         st = torch.empty(k, dtype=torch.float64, device=dev)
         it = torch.empty(k, dtype=torch.int32, device=dev)
-        fjofc.fjofc_oos(ctx, prob.X, prob.wmat, dnew, Ystart, cfg.oos_iters, target=target,
-                        stress_out=st, iters_out=it, sync=False)
-        return st, it
-
-    # learned warm start: features + network + refinement, timed together
-    dims = net.dims
-    inf_batch = 8192
-    ninf = fjofc.Mlp(ctx, dims, inf_batch)
-    ninf.set_params(*net.get_params())
-    x = torch.empty((k, sp.m * cfg.landmarks), dtype=torch.bfloat16, device=dev)
-    Yw = torch.empty((k, sp.m, sp.d), dtype=torch.float32, device=dev)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    fjofc.fjofc_mlp_features(ctx, dnew, landmarks, mu, inv_sd, x)
-    for o0 in range(0, k, inf_batch):
-        o1 = min(k, o0 + inf_batch)
-        ninf.predict_start(x[o0:o1], Yw[o0:o1])
-    st_w, it_w = refine(Yw)
-    torch.cuda.synchronize()
-    t_warm = time.perf_counter() - t0
-    ninf.close()
-
-    # nearest-in-sample start (comparison)
-    Yn = torch.empty((k, sp.m, sp.d), dtype=torch.float32, device=dev)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    fjofc.fjofc_oos_nearest_start(ctx, prob.X, dnew, Yn)
-    st_n, it_n = refine(Yn)
-    torch.cuda.synchronize()
-    t_nn = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for o0 in range(0, k, nb):
+            o1 = min(k, o0 + nb)
+            start_fn(o0, o1, Y)
+            refine(Y, o0, o1, st, it)
+        torch.cuda.synchronize()
+        return st, it, time.perf_counter() - t0
 
     def summ(st, it, t):
         itn = it.cpu().numpy()
@@ -260,43 +263,85 @@ def evaluate(ctx, prob, net, mu, inv_sd, landmarks, cfg: WarmStartConfig, k: int
                 "iters_p99": float(np.percentile(itn, 99)),
                 "reached_frac": float(ok.mean())}
 
-    res = {"objects": k, "rel": cfg.rel, "oos_iters_cap": cfg.oos_iters,
+    res = {"objects": k, "rel": cfg.rel, "oos_iters_cap": cfg.oos_iters, "call_objects": nb,
            "plain": {"seconds": t_plain, "iters": cfg.oos_iters,
-                     "mean_stress": float(sp_stress.mean())},
-           "warm": summ(st_w, it_w, t_warm),
-           "nearest": summ(st_n, it_n, t_nn)}
-    res["speedup_vs_plain"] = t_plain / res["warm"]["seconds"]
-    res["speedup_vs_nearest"] = t_nn / res["warm"]["seconds"]
-    log(f"[warmstart] plain {t_plain:.4f}s; warm {t_warm:.4f}s "
-        f"(mean {res['warm']['iters_mean']:.1f} iters, reached {res['warm']['reached_frac']:.3f}); "
-        f"nearest {t_nn:.4f}s (mean {res['nearest']['iters_mean']:.1f}, "
-        f"reached {res['nearest']['reached_frac']:.3f})")
+                     "mean_stress": float(sp_stress.mean())}}
+
+    # the plain start again, stopped by the same target rule
+    def plain_copy(o0, o1, Y):
+        Y[o0:o1].copy_(Y0[o0:o1])
+    res["plain_target"] = summ(*timed(plain_copy))
+
+    # learned starts: features + network + refinement, timed together
+    x = torch.empty((k, sp.m * cfg.landmarks), dtype=torch.bfloat16, device=dev)
+    for name, (net, mu, inv_sd) in nets.items():
+        ninf = fjofc.Mlp(ctx, net.dims, nb)
+        ninf.set_params(*net.get_params())
+
+        def learned(o0, o1, Y, ninf=ninf, mu=mu, inv_sd=inv_sd):
+            fjofc.fjofc_mlp_features(ctx, dnew[o0:o1], landmarks, mu, inv_sd, x[o0:o1])
+            ninf.predict_start(x[o0:o1], Y[o0:o1])
+        res[name] = summ(*timed(learned))
+        res[name]["outputs"] = net.dims[-1]
+        ninf.close()
+
+    # nearest-in-sample start (comparison)
+    def nearest(o0, o1, Y):
+        fjofc.fjofc_oos_nearest_start(ctx, prob.X, dnew[o0:o1], Y[o0:o1])
+    res["nearest"] = summ(*timed(nearest))
+
+    w = res["warm"]
+    res["speedup_vs_plain"] = t_plain / w["seconds"]
+    res["speedup_vs_plain_target"] = res["plain_target"]["seconds"] / w["seconds"]
+    res["speedup_vs_nearest"] = res["nearest"]["seconds"] / w["seconds"]
+    for name in ["plain_target", *nets.keys(), "nearest"]:
+        r = res[name]
+        log(f"[warmstart] {name}: {r['seconds']:.4f}s, mean {r['iters_mean']:.1f} transforms, "
+            f"reached {r['reached_frac']:.4f}")
+    log(f"[warmstart] plain reference {t_plain:.4f}s")
     return res
 
 
 def run(ctx, cfg: Optional[WarmStartConfig] = None, eval_objects: int = 50000, log=print,
-        spec=None):
+        spec=None, ablation: bool = False):
     """The whole learned warm-start workload; returns a summary dict.  `spec`
-    defaults to the out-of-sample workload (m=2, n=10000, d=5)."""
+    defaults to the out-of-sample workload (m=2, n=10000, d=5).  The network
+    of cfg is reported as "warm"; with `ablation` a second network with the
+    other output layout (per-modality points vs one consensus point) is
+    trained on the same objects and reported beside it."""
+    import dataclasses
     import torch
     from workloads import generators as gen
     cfg = cfg or WarmStartConfig()
     spec = spec or gen.config2_spec()
     dev = torch.device("cuda:0")
-    t0 = time.perf_counter()
     prob = Problem(ctx, spec, dev)
     rng = np.random.default_rng(cfg.seed_landmarks)
     landmarks = torch.from_numpy(rng.choice(spec.n, cfg.landmarks, replace=False)
                                  .astype(np.int32)).to(dev)
-    raw, tgt = training_data(ctx, prob, cfg, landmarks, log)
+    cfgs = {"warm": cfg}
+    if ablation:
+        alt = "warm_per_modality" if not cfg.per_modality else "warm_consensus"
+        cfgs[alt] = dataclasses.replace(cfg, per_modality=not cfg.per_modality)
+    nets, info = {}, {}
     t1 = time.perf_counter()
-    net, mu, inv_sd, hist = train_network(ctx, raw, tgt, cfg, log)
+    raw, Yt = training_data(ctx, prob, cfg, landmarks, log)
     torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    del raw, tgt
-    ev = evaluate(ctx, prob, net, mu, inv_sd, landmarks, cfg, eval_objects, log)
-    net.close()
+    t_data = time.perf_counter() - t1
+    for name, c in cfgs.items():
+        t2 = time.perf_counter()
+        net, mu, inv_sd, hist = train_network(ctx, raw, targets(ctx, Yt, c.per_modality), c, log)
+        torch.cuda.synchronize()
+        nets[name] = (net, mu, inv_sd)
+        info[name] = {"outputs": net.dims[-1], "per_modality": c.per_modality,
+                      "train_seconds": time.perf_counter() - t2,
+                      "final_val_mse": hist[-1]["val_mse"]}
+    del raw, Yt
+    ev = evaluate(ctx, prob, nets, landmarks, cfg, eval_objects, log)
+    for net, _, _ in nets.values():
+        net.close()
     return {"workload": f"warm_start_m{spec.m}_n{spec.n}_d{spec.d}",
-            "train_objects": cfg.train_objects,
-            "epochs": cfg.epochs, "data_seconds": t1 - t0, "train_seconds": t2 - t1,
-            "final_val_mse": hist[-1]["val_mse"], "eval": ev}
+            "train_objects": cfg.train_objects, "epochs": cfg.epochs,
+            "networks": info, "data_seconds": t_data,
+            "train_seconds": info["warm"]["train_seconds"],
+            "final_val_mse": info["warm"]["final_val_mse"], "eval": ev}

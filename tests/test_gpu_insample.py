@@ -129,6 +129,28 @@ def test_one_transform_parity_table_tiles_mid_sizes(ctx, m, n, d):
     assert rg["stress"] == pytest.approx(orc.stress(delta, wmat, X1o)[0], rel=2e-5)
 
 
+@pytest.mark.parametrize("tile,n", [("264:1", 268), ("264:1", 530), ("392:0", 300)])
+def test_tall_tiles_padding_rows(ctx, monkeypatch, tile, n):
+    """A tile taller than it is wide gives a row padding that is not a
+    multiple of the finalize's 256-row blocks, so the finalize never writes
+    the last padding rows that boundary tiles read (masked).  They must
+    hold zeros even when the workspace held NaN before: after a run of a
+    larger problem from an all-NaN configuration (which leaves NaN across
+    the context workspace), 3 transforms against the oracle."""
+    m, d = 2, 3
+    big, _, _ = _problem(299, m, 1500, d)
+    Xnan = np.full((m * 1500, d), np.nan, np.float32)
+    fjofc.fjofc_embed(ctx, [_dev(x) for x in big], gen.uniform_wmat(m, 0.5), _dev(Xnan), 2)
+    monkeypatch.setenv("FJOFC_TILE", tile)
+    wmat = _general_wmat(m, seed=n)
+    delta, _, X0 = _problem(300 + n, m, n, d, wmat=wmat)
+    Xo, ro, _ = orc.embed(delta, wmat, X0, 3)
+    Xg, rg, _ = _gpu_embed(ctx, delta, wmat, X0, 3)
+    assert np.all(np.isfinite(Xg))
+    np.testing.assert_allclose(Xg, Xo, rtol=0, atol=2e-5 * np.abs(Xo).max())
+    assert rg["stress"] == pytest.approx(ro["stress"], rel=2e-5)
+
+
 def test_stress_entry_point(ctx):
     m, n, d = 3, 333, 4
     wmat = _general_wmat(m)
@@ -152,22 +174,62 @@ def test_many_iterations_parity_general_w(ctx):
     assert _rel_fro(Xg, Xo) <= 1e-4
 
 
-def test_stop_rule_matches_oracle(ctx):
+# (seed, tol_mode, tol, stress_every): cases whose every checkpoint decision
+# lies at least 1e-4 (relative to the previous stress) away from the
+# threshold in the oracle, so FP32 rounding cannot flip any of them.
+STOP_CASES = [(12, 1, 5e-3, 1), (12, 1, 1e-2, 5), (43, 1, 1e-3, 1), (41, 1, 2e-3, 5),
+              (12, 2, 1e-4, 1), (12, 2, 2e-4, 5), (43, 2, 1e-4, 1), (41, 2, 1e-4, 5)]
+
+
+@pytest.mark.parametrize("seed,mode,tol,every", STOP_CASES)
+def test_stop_rule_matches_oracle(ctx, seed, mode, tol, every):
+    """Algorithm 2's stop test (relative and the paper's normalised form):
+    the GPU stops at the oracle's transform and returns its X.  Every
+    checkpoint's decision margin is asserted first, so the comparison is
+    never skipped."""
+    m, n, d = 2, 300, 2
+    delta, wmat, X0 = _problem(seed, m, n, d)
+    Xo, ro, ho = orc.embed(delta, wmat, X0, 500, tol=tol, tol_mode=mode, stress_every=every)
+    t = ro["iters_run"]
+    assert ro["converged"] == 1 and 0 < t < 500
+    for c in range(every, t + 1, every):
+        prev = ho[c - every]
+        thr = tol * prev if mode == 1 else tol * (m * n) * (m * n - 1) / 2
+        assert abs((prev - ho[c]) - thr) / prev >= 1e-4, f"checkpoint {c} within noise"
+    Xg, rg, hg = _gpu_embed(ctx, delta, wmat, X0, 500, tol=tol, tol_mode=mode,
+                            stress_every=every, want_hist=True)
+    assert rg["iters_run"] == t and rg["converged"] == 1
+    assert _rel_fro(Xg, Xo) <= 1e-4
+    assert rg["stress"] == pytest.approx(ro["stress"], rel=1e-5)
+    ok = ~np.isnan(ho[: t + 1])
+    np.testing.assert_allclose(hg[: t + 1][ok], ho[: t + 1][ok], rtol=1e-5)
+
+
+def test_early_stop_enqueues_at_most_one_chunk_past_the_stop(ctx):
+    """A run capped at 5000 transforms that stops after a few: transforms
+    are enqueued in chunks of 32 and the host checks the done flag of the
+    chunk before the one it just enqueued, so at most two chunks of stream
+    launches are issued before the stop is seen (plus the closing stress
+    pass), and the result is the oracle's."""
     m, n, d = 2, 300, 2
     delta, wmat, X0 = _problem(12, m, n, d)
-    for mode, tol, every in [(1, 1e-3, 1), (1, 2e-3, 5), (2, 1e-5, 1), (2, 3e-5, 2)]:
-        Xo, ro, ho = orc.embed(delta, wmat, X0, 500, tol=tol, tol_mode=mode, stress_every=every)
-        Xg, rg, hg = _gpu_embed(ctx, delta, wmat, X0, 500, tol=tol, tol_mode=mode,
-                                stress_every=every, want_hist=True)
-        t = ro["iters_run"]
-        assert ro["converged"] == 1 and 0 < t < 500
-        # the decision at the stop must not be within FP32 noise of the threshold
-        prev = ho[t - every]
-        thr = tol * prev if mode == 1 else tol * (m * n) * (m * n - 1) / 2
-        margin = abs((prev - ho[t]) - thr) / prev
-        if margin > 1e-5:
-            assert rg["iters_run"] == t and rg["converged"] == 1
-            assert _rel_fro(Xg, Xo) <= 1e-4
+    tol, every = 0.2, 1
+    Xo, ro, ho = orc.embed(delta, wmat, X0, 5000, tol=tol, tol_mode=1, stress_every=every)
+    t = ro["iters_run"]
+    assert ro["converged"] == 1 and 0 < t < 32
+    for c in range(1, t + 1):
+        assert abs((ho[c - 1] - ho[c]) / ho[c - 1] - tol) >= 1e-4
+    fjofc.fjofc_profile_enable(ctx, True)
+    try:
+        Xg, rg, _ = _gpu_embed(ctx, delta, wmat, X0, 5000, tol=tol, tol_mode=1,
+                               stress_every=every)
+        prof = fjofc.fjofc_profile_read(ctx)
+    finally:
+        fjofc.fjofc_profile_enable(ctx, False)
+    assert rg["iters_run"] == t and rg["converged"] == 1
+    assert _rel_fro(Xg, Xo) <= 1e-4
+    assert prof["stream_launches"] <= 2 * 32
+    assert prof["edge_launches"] == 1
 
 
 def test_zero_iterations_and_coincident_points(ctx):

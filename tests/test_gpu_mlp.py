@@ -2,9 +2,15 @@
 accumulation) against the FP64 oracle with the same BF16 rounding points.
 
 The two sides round to BF16 at the same places, but from FP32 vs FP64
-sums, so an activation that lands near a BF16 rounding boundary can differ
-by one BF16 step (2^-8 relative) in a few elements.  Outputs and gradients
-are therefore compared by relative Frobenius norm at 2e-3.
+sums, so an activation or gradient that lands near a BF16 rounding boundary
+can round one BF16 step apart, and that step reaches later products.
+Outputs and gradients are therefore compared element by element in units
+of one BF16 step (2^-7 of the element's binade, taken at least at the
+array's RMS so that elements near zero are judged on the array's scale):
+every element within one step, and at most 0.1% of them (and at least 2
+allowed) beyond half a step.  An FP32-accumulation emulation of the GPU's
+arithmetic on the host stays within 0.53 step, with 5 of 262144 elements
+beyond half a step in the widest gradient.
 """
 import numpy as np
 import pytest
@@ -30,6 +36,23 @@ def ctx():
 
 def _rel(a, b):
     return np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _bf16_steps(g, o):
+    """|g - o| in BF16 steps of max(|o|, rms(o)) per element."""
+    o = np.asarray(o, np.float64)
+    g = np.asarray(g, np.float64)
+    rms = np.sqrt((o * o).mean()) if o.size else 0.0
+    ref = np.maximum(np.maximum(np.abs(o), rms), 1e-30)
+    step = 2.0 ** (np.floor(np.log2(ref)) - 7)
+    return np.abs(g - o) / step
+
+
+def _assert_bf16_close(g, o, what):
+    s = _bf16_steps(g, o)
+    assert s.max() <= 1.0, f"{what}: {s.max():.3f} BF16 steps at {np.unravel_index(s.argmax(), s.shape)}"
+    cap = max(2, int(1e-3 * s.size))
+    assert (s > 0.5).sum() <= cap, f"{what}: {(s > 0.5).sum()} elements beyond half a step"
 
 
 def _net(ctx, dims, B, seed):
@@ -62,11 +85,11 @@ def test_forward_and_gradients(ctx, monkeypatch, dims, B, waves):
     torch.cuda.synchronize()
     lo, go, oo = omlp.loss_and_grads([(W.astype(np.float64), b.astype(np.float64))
                                       for W, b in params], x, y, bf16=True)
-    assert _rel(out.cpu().numpy(), oo) < 2e-3
-    assert abs(loss.item() - lo) <= 2e-3 * lo
+    _assert_bf16_close(out.cpu().numpy(), oo, "output")
+    assert abs(loss.item() - lo) <= 1e-3 * lo
     for l, (gW, gb) in enumerate(go):
-        assert _rel(dW[l].cpu().numpy(), gW) < 2e-3, f"dW[{l}]"
-        assert _rel(db[l].cpu().numpy(), gb) < 2e-3, f"db[{l}]"
+        _assert_bf16_close(dW[l].cpu().numpy(), gW, f"dW[{l}]")
+        _assert_bf16_close(db[l].cpu().numpy(), gb, f"db[{l}]")
 
 
 def test_adam_step_matches_oracle(ctx):
@@ -88,6 +111,39 @@ def test_adam_step_matches_oracle(ctx):
         dWo = Wo - params[l][0]
         assert _rel(dWg, dWo) < 2e-2, f"W[{l}]"
         assert _rel(b[l].cpu().numpy() - params[l][1], bo - params[l][1]) < 2e-2
+
+
+def test_adam_kernel_elementwise(ctx):
+    """The Adam kernel alone, element by element: three steps driven by the
+    GPU's own gradients, against the oracle's FP64 Adam fed the same
+    gradients.  Each parameter moves by about lr per step; the two sides
+    differ only by FP32 rounding of the moments and of the parameter."""
+    dims, B = [48, 40, 6], 96
+    net, params, x, y, xb = _net(ctx, dims, B, 13)
+    yt = torch.from_numpy(y).cuda()
+    W0, b0 = net.get_params()
+    p64 = [(Wq.cpu().numpy().astype(np.float64), bq.cpu().numpy().astype(np.float64))
+           for Wq, bq in zip(W0, b0)]
+    opt = omlp.Adam(p64)
+    for step, lr in enumerate((1e-3, 2e-3, 5e-4)):
+        net.backward(xb, yt)
+        dW, db = net.get_grads()
+        g64 = [(gW.cpu().numpy().astype(np.float64), gb.cpu().numpy().astype(np.float64))
+               for gW, gb in zip(dW, db)]
+        net.adam(lr)
+        p64 = opt.step(p64, g64, lr)
+        W, b = net.get_params()
+        torch.cuda.synchronize()
+        for l, (Wo, bo) in enumerate(p64):
+            for got, want, name in ((W[l], Wo, "W"), (b[l], bo, "b")):
+                got = got.cpu().numpy().astype(np.float64)
+                # FP32 rounding of the stored parameter plus 1e-4 of the
+                # step's size for the FP32 moments
+                tol = 2.0 * np.spacing(np.abs(want).astype(np.float32)) + 1e-4 * lr
+                assert np.all(np.abs(got - want) <= tol), f"step {step} {name}[{l}]"
+        # continue both sides from the GPU's FP32 parameters
+        p64 = [(Wq.cpu().numpy().astype(np.float64), bq.cpu().numpy().astype(np.float64))
+               for Wq, bq in zip(W, b)]
 
 
 def test_training_reduces_loss(ctx):
@@ -142,3 +198,49 @@ def test_predict_start_rejects_other_widths(ctx):
     net, _, _, _, xb = _net(ctx, [24, 32, 7], 10, 5)
     with pytest.raises(fjofc.FjofcError):
         net.predict_start(xb, torch.empty((10, 2, 5), device="cuda"))
+
+
+@pytest.mark.parametrize("N,F", [(1, 5), (37, 3), (1000, 300), (5003, 512)])
+def test_feature_stats(ctx, N, F):
+    """fjofc_mlp_feature_stats against the oracle's mean and sample SD; one
+    constant column takes min_sd."""
+    rng = np.random.default_rng(N + F)
+    raw = (rng.standard_normal((N, F)) * rng.uniform(0.1, 5, F) + rng.uniform(-3, 3, F))
+    raw = raw.astype(np.float32)
+    raw[:, F // 2] = 1.25
+    mu = torch.empty(F, dtype=torch.float32, device="cuda")
+    isd = torch.empty_like(mu)
+    fjofc.fjofc_mlp_feature_stats(ctx, torch.from_numpy(raw).cuda(), mu, isd, min_sd=1e-3)
+    mo, io = omlp.feature_stats(raw, 1e-3)
+    np.testing.assert_allclose(mu.cpu().numpy(), mo, rtol=1e-6, atol=1e-7 * np.abs(mo).max())
+    np.testing.assert_allclose(isd.cpu().numpy(), io, rtol=2e-6)
+    assert isd[F // 2].item() == pytest.approx(1e3, rel=1e-6)
+
+
+@pytest.mark.parametrize("k,m,d", [(1, 1, 1), (37, 2, 5), (4096, 3, 2)])
+def test_consensus_points(ctx, k, m, d):
+    rng = np.random.default_rng(k)
+    Y = rng.standard_normal((k, m, d)).astype(np.float32)
+    out = torch.empty((k, d), dtype=torch.float32, device="cuda")
+    fjofc.fjofc_oos_consensus(ctx, torch.from_numpy(Y).cuda(), out)
+    np.testing.assert_allclose(out.cpu().numpy(), omlp.consensus(Y), rtol=1e-6, atol=1e-7)
+
+
+@pytest.mark.parametrize("dims,B", [([64, 48, 40, 5], 37), ([512, 512, 512, 512, 5], 1024)])
+def test_loss_only(ctx, dims, B):
+    """fjofc_mlp_loss: the oracle's MSE at the BF16 rounding points; the
+    stored gradients are not touched."""
+    net, params, x, y, xb = _net(ctx, dims, B, 31 + B)
+    yt = torch.from_numpy(y).cuda()
+    net.backward(xb, yt)
+    dW0, _ = net.get_grads()
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    net.loss(xb, yt, loss)
+    dW1, _ = net.get_grads()
+    torch.cuda.synchronize()
+    lo, _, _ = omlp.loss_and_grads([(W.astype(np.float64), b.astype(np.float64))
+                                    for W, b in params], x, y, bf16=True)
+    assert abs(loss.item() - lo) <= 1e-3 * lo
+    for a, b in zip(dW0, dW1):
+        assert torch.equal(a, b)
+

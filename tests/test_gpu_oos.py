@@ -33,10 +33,20 @@ def _dev(a, dt=np.float32):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).cuda()
 
 
-def _oos_problem(seed, m, n, d, k, lat=4, sigma=0.2, in_iters=30):
+def _general_wmat(m, seed):
+    """eq:W2 weights with unequal fidelity weights w_ii and unequal
+    commensurability weights w_ik (symmetric, as the ABI requires)."""
+    rng = np.random.default_rng(seed)
+    W = rng.uniform(0.2, 2.0, size=(m, m))
+    W = 0.5 * (W + W.T)
+    np.fill_diagonal(W, rng.uniform(0.5, 2.0, size=m))
+    return W
+
+
+def _oos_problem(seed, m, n, d, k, lat=4, sigma=0.2, in_iters=30, weights="uniform"):
     views, maps, X0 = gen.latent_views(seed, n, m, lat, sigma, d)
     delta = [gen.pairwise_dist_np(Y).astype(np.float32) for Y in views]
-    wmat = gen.uniform_wmat(m, 0.5)
+    wmat = gen.uniform_wmat(m, 0.5) if weights == "uniform" else _general_wmat(m, seed + 7)
     X, _, _ = orc.embed(delta, wmat, X0, in_iters)
     X = X.astype(np.float32)
     new = gen.oos_objects(seed + 1, k, maps, sigma)
@@ -58,17 +68,23 @@ def _run(ctx, X, wmat, dnew, Y0, iters, **kw):
     return Y.cpu().numpy().astype(np.float64), st.cpu().numpy(), it.cpu().numpy()
 
 
+@pytest.mark.parametrize("weights", ["uniform", "general"])
 @pytest.mark.parametrize("ob", [None, "1", "2", "4"])
 @pytest.mark.parametrize("m,n,d,k", [(2, 200, 2, 9), (3, 257, 3, 17), (2, 1000, 5, 40),
                                      (1, 100, 2, 8), (4, 64, 8, 5), (2, 3, 1, 3), (8, 300, 3, 6),
                                      (2, 1536, 4, 13)])
-def test_oos_parity(ctx, monkeypatch, m, n, d, k, ob):
+def test_oos_parity(ctx, monkeypatch, m, n, d, k, ob, weights):
     """Against the oracle for 0, 1 and 25 transforms; with the default four
     objects per workgroup or with 1, 2 or 4 forced (k not a multiple of
-    them leaves a partly filled last workgroup)."""
+    them leaves a partly filled last workgroup).  With uniform eq:W weights
+    and with general eq:W2 weights (unequal w_ii and w_ik), for which the
+    update is the derived one: fidelity weight w_ii on the new copy's
+    in-sample pairs and L22 the eq:modW matrix."""
     if ob:
         monkeypatch.setenv("FJOFC_OOS_OB", ob)
-    X, wmat, dnew, Y0 = _oos_problem(30 + n, m, n, d, k)
+    X, wmat, dnew, Y0 = _oos_problem(30 + n, m, n, d, k, weights=weights)
+    if weights == "general" and m > 1:
+        assert len(np.unique(np.diag(wmat))) == m
     for iters in (0, 1, 25):
         Yo, so, io = orc.oos(X, wmat, dnew, Y0, iters)
         Yg, sg, ig = _run(ctx, X, wmat, dnew, Y0, iters)

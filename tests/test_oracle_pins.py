@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 from oracle import dense, structured as orc
+from oracle import dense as odense
 from workloads import generators as gen
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
@@ -525,3 +526,29 @@ def test_paper_init_of_congruent_views_has_zero_stress():
     total = sum((x.astype(np.float64) ** 2).sum() / 2 for x in delta)
     assert s <= 1e-9 * total
     np.testing.assert_allclose(eig[1:], np.repeat(eig[:1], 3, axis=0), rtol=1e-6)
+
+
+def test_first_invalid_scan_on_hand_built_matrices():
+    """The dissimilarity check of the oracle on matrices whose first bad
+    entry is known by construction (Section 1: Delta in R_+^{n x n},
+    symmetric, zero diagonal)."""
+    base = np.array([[0, 1, 2], [1, 0, 3], [2, 3, 0]], np.float32)
+    assert odense.first_invalid(base) == (-1, 0)
+    # symmetric changes, so only the value rule or the diagonal rule fires
+    cases = [((1, 2), np.nan, (5, 1)), ((2, 0), np.inf, (2, 2)), ((0, 2), -1.0, (2, 3)),
+             ((1, 1), 0.5, (4, 5))]
+    for (i, j), v, want in cases:
+        D = base.copy()
+        D[i, j] = v
+        D[j, i] = v
+        assert odense.first_invalid(D) == want
+    # an asymmetric pair is reported at its upper-triangle entry, even when
+    # only the lower one was changed
+    D = base.copy()
+    D[2, 1] = 7.0
+    assert odense.first_invalid(D) == (1 * 3 + 2, 4)
+    # of two offences the earlier in row-major order wins
+    D = base.copy()
+    D[2, 2] = 1.0
+    D[0, 1] = -2.0
+    assert odense.first_invalid(D) == (1, 3)
