@@ -216,6 +216,28 @@ int fjofc_oos(fjofc_ctx *ctx, const float *X_in, int m, int n, int d,
               int *iters_out, int sync, void *stream);
 
 /*
+ * Allocation-free form of fjofc_oos, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Arguments, results and kernels are
+ * those of fjofc_oos (the results are bitwise equal); the differences:
+ *  - its working memory (the SoA copy of X_in, column sums, L22^-1 and the
+ *    weights) is a 4 MiB array of device memory that the library holds per
+ *    GPU from fjofc_create until the process ends; nothing is allocated,
+ *    and m x m matrices reach the device as a kernel argument;
+ *  - limits: m <= 8 and 4 (m d npad) + 8 (m d + 2 m^2) bytes (each piece
+ *    rounded up to 256) <= 4 MiB, npad = n rounded up to 256 (e.g. m = 2,
+ *    d = 5, n <= about 104000); larger problems return FJOFC_EINVAL;
+ *  - every call on one GPU shares that GPU's array: calls that overlap in
+ *    time on one GPU (other streams, other threads) race and must be
+ *    serialised by the caller; each call rewrites all it reads;
+ *  - no profiling records and no FJOFC_VALIDATE pass.
+ */
+int fjofc_oos_noalloc(fjofc_ctx *ctx, const float *X_in, int m, int n, int d,
+                      const double *wmat, const float *delta_new, int k, float *Y,
+                      int iters, double tol, const double *target, double *stress_out,
+                      int *iters_out, int sync, void *stream);
+
+/*
  * Nearest-in-sample start for fjofc_oos (a comparison start; the paper
  * starts from a random point): Y[o][i] = row i*n + j* of X_in, j* being the
  * smallest index minimising delta_new[o][i][j] over j.  Arrays as for

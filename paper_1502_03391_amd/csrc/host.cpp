@@ -14,6 +14,7 @@
 #include <array>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <string>
 #include <vector>
@@ -795,6 +796,177 @@ void batch_free(fjofc_batch *b) {
 
 }  // namespace
 
+// ---- scratch of the allocation-free out-of-sample call ----------------
+// A file-scope device array: each GPU the library runs on holds its own
+// copy until the process ends.  Host code never uses the array's name as a
+// device address; the address is taken once per device with
+// hipGetSymbolAddress (fjofc_create, with that device current) and kept in
+// g_scratch.  Every allocation-free call on a GPU shares that GPU's array,
+// so such calls that overlap on one GPU race.
+constexpr size_t kNoAllocBytes = size_t(4) << 20;
+constexpr int kNoAllocMaxM = 8;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {};
+
+// Takes the scratch address of `dev`, which must be the current device.
+int init_noalloc_scratch(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(FJOFC_EINVAL, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch[dev]) return FJOFC_OK;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return fail(FJOFC_EHIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                    hipGetErrorString(e));
+    g_scratch[dev] = p;
+    return FJOFC_OK;
+}
+
+int noalloc_scratch(int dev, void **p) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(FJOFC_EINVAL, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    *p = g_scratch[dev];
+    if (!*p) return fail(FJOFC_EINVAL, "scratch of device %d not set up (fjofc_create)", dev);
+    return FJOFC_OK;
+}
+
+// W^-1 and the weights of a problem with m <= kNoAllocMaxM, passed by value.
+struct SmallMats {
+    double a[kNoAllocMaxM * kNoAllocMaxM];
+    double b[kNoAllocMaxM * kNoAllocMaxM];
+    int count;
+};
+
+__global__ void noalloc_mats_kernel(SmallMats mats, double *__restrict__ a,
+                                    double *__restrict__ b) {
+    for (int q = threadIdx.x; q < mats.count; q += blockDim.x) {
+        a[q] = mats.a[q];
+        b[q] = mats.b[q];
+    }
+}
+
+// fjofc_oos and its allocation-free variant.  With `noalloc` the SoA copy
+// of X_in, the column sums and the two m x m matrices live in the
+// module-scope scratch array (reached through its per-device address), the
+// matrices travel as a kernel argument, and nothing is allocated, timed or
+// validated.
+int oos_run(fjofc_ctx *ctx, const float *X_in, int m, int n, int d, const double *wmat,
+            const float *delta_new, int k, float *Y, int iters, double tol,
+            const double *target, double *stress_out, int *iters_out, int sync, void *stream,
+            bool noalloc) {
+    if (!ctx) return fail(FJOFC_EINVAL, "ctx is NULL");
+    if (m < 1 || m > FJOFC_MAX_M) return fail(FJOFC_EINVAL, "m=%d outside [1,%d]", m, FJOFC_MAX_M);
+    if (n < 1) return fail(FJOFC_EINVAL, "n=%d must be >= 1", n);
+    if (d < 1 || d > FJOFC_MAX_D) return fail(FJOFC_EINVAL, "d=%d outside [1,%d]", d, FJOFC_MAX_D);
+    if (k < 0) return fail(FJOFC_EINVAL, "k=%d must be >= 0", k);
+    if (iters < 0) return fail(FJOFC_EINVAL, "iters must be >= 0");
+    if (!X_in || (k > 0 && (!delta_new || !Y))) return fail(FJOFC_EINVAL, "NULL array");
+    int rc = check_weights(m, wmat);
+    if (rc) return rc;
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (noalloc && m > kNoAllocMaxM)
+        return fail(FJOFC_EINVAL, "m=%d: the allocation-free call takes m <= %d", m,
+                    kNoAllocMaxM);
+    if (!noalloc && validate_on() && k > 0) {
+        rc = ensure_vslot(ctx);
+        if (rc) return rc;
+        HIP_TRY(launch_validate_rows(delta_new, (long long)k * m * n, ctx->vslot, true, s));
+        unsigned long long code = 0;
+        rc = read_vslot(ctx, s, &code);
+        if (rc) return rc;
+        if (code != ~0ull) {
+            const long long idx = (long long)(code >> 3), row = idx / n;
+            return fail(FJOFC_EINVAL, "delta_new: object %lld, modality %lld, entry %lld %s",
+                        row / m, row % m, idx % n, offence_name((int)(code & 7)));
+        }
+    }
+
+    std::vector<double> W((size_t)m * m), Li((size_t)m * m);
+    wmod(m, n, wmat, W.data());
+    if (!invert(m, W.data(), Li.data()))
+        return fail(FJOFC_ESINGULAR, "eq:modW matrix is singular");
+
+    TriGeom g{};
+    g.n = n;
+    g.m = m;
+    g.npad = (n + 255) / 256 * 256;
+    Carve cv;
+    const size_t oX = cv.take<float>((size_t)m * d * g.npad);
+    const size_t oC = cv.take<double>((size_t)m * d);
+    const size_t oL = cv.take<double>((size_t)m * m);
+    const size_t oW = cv.take<double>((size_t)m * m);
+    char *b = nullptr;
+    if (noalloc) {
+        if (cv.off > kNoAllocBytes)
+            return fail(FJOFC_EINVAL,
+                        "m=%d, n=%d, d=%d needs %zu bytes of scratch; the allocation-free call "
+                        "has %zu (m d npad <= about %zu floats, npad = n rounded up to 256)",
+                        m, n, d, cv.off, kNoAllocBytes, kNoAllocBytes / 4);
+        void *sp = nullptr;
+        rc = noalloc_scratch(ctx->device, &sp);
+        if (rc) return rc;
+        b = static_cast<char *>(sp);
+    } else {
+        rc = ensure_ws(ctx, cv.off);
+        if (rc) return rc;
+        b = static_cast<char *>(ctx->ws);
+    }
+    float *Xs = reinterpret_cast<float *>(b + oX);
+    double *colsum = reinterpret_cast<double *>(b + oC);
+    double *dLi = reinterpret_cast<double *>(b + oL);
+    double *dW = reinterpret_cast<double *>(b + oW);
+    if (noalloc) {
+        SmallMats mats{};
+        for (int q = 0; q < m * m; ++q) {
+            mats.a[q] = Li[q];
+            mats.b[q] = wmat[q];
+        }
+        mats.count = m * m;
+        noalloc_mats_kernel<<<1, 64, 0, s>>>(mats, dLi, dW);
+        HIP_TRY(hipGetLastError());
+    } else {
+        HIP_TRY(hipMemcpyAsync(dLi, Li.data(), sizeof(double) * m * m, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(dW, wmat, sizeof(double) * m * m, hipMemcpyHostToDevice, s));
+    }
+    HIP_TRY(launch_to_soa(g, d, X_in, Xs, s));
+
+    OOSArgs a;
+    a.Xs = Xs;
+    a.m = m;
+    a.n = n;
+    a.npad = g.npad;
+    a.D = d;
+    a.dnew = delta_new;
+    a.k = k;
+    a.Y = Y;
+    a.Linv = dLi;
+    a.wmat = dW;
+    a.target = target;
+    a.stress_out = stress_out;
+    a.iters_out = iters_out;
+    a.tol = tol;
+    a.iters = iters;
+    a.ob = 0;  // the default objects per workgroup
+    a.vec4 = (n % 4 == 0 && (reinterpret_cast<uintptr_t>(delta_new) & 15) == 0 &&
+              !std::getenv("FJOFC_OOS_SCALAR")) ? 1 : 0;
+    if (noalloc) {
+        HIP_TRY(launch_oos(a, colsum, s));
+    } else {
+        Timed tm(ctx, K_OOS, 4.0 * (double)k * m * n * (iters + 1), s);
+        HIP_TRY(launch_oos(a, colsum, s));
+    }
+    if (sync) HIP_TRY(hipStreamSynchronize(s));
+    return FJOFC_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *fjofc_last_error(void) { return g_err.c_str(); }
@@ -816,6 +988,11 @@ int fjofc_create(fjofc_ctx **out, int device) {
     HIP_TRY(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev)
         return fail(FJOFC_EINVAL, "device %d not present (%d devices)", device, ndev);
+    {
+        DeviceGuard dg(device);
+        const int rc = init_noalloc_scratch(device);
+        if (rc) return rc;
+    }
     fjofc_ctx *c = new fjofc_ctx();
     c->device = device;
     *out = c;
@@ -885,81 +1062,16 @@ int fjofc_oos(fjofc_ctx *ctx, const float *X_in, int m, int n, int d,
               const double *wmat, const float *delta_new, int k, float *Y,
               int iters, double tol, const double *target, double *stress_out,
               int *iters_out, int sync, void *stream) {
-    if (!ctx) return fail(FJOFC_EINVAL, "ctx is NULL");
-    if (m < 1 || m > FJOFC_MAX_M) return fail(FJOFC_EINVAL, "m=%d outside [1,%d]", m, FJOFC_MAX_M);
-    if (n < 1) return fail(FJOFC_EINVAL, "n=%d must be >= 1", n);
-    if (d < 1 || d > FJOFC_MAX_D) return fail(FJOFC_EINVAL, "d=%d outside [1,%d]", d, FJOFC_MAX_D);
-    if (k < 0) return fail(FJOFC_EINVAL, "k=%d must be >= 0", k);
-    if (iters < 0) return fail(FJOFC_EINVAL, "iters must be >= 0");
-    if (!X_in || (k > 0 && (!delta_new || !Y))) return fail(FJOFC_EINVAL, "NULL array");
-    int rc = check_weights(m, wmat);
-    if (rc) return rc;
-    DeviceGuard dg(ctx->device);
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    if (validate_on() && k > 0) {
-        rc = ensure_vslot(ctx);
-        if (rc) return rc;
-        HIP_TRY(launch_validate_rows(delta_new, (long long)k * m * n, ctx->vslot, true, s));
-        unsigned long long code = 0;
-        rc = read_vslot(ctx, s, &code);
-        if (rc) return rc;
-        if (code != ~0ull) {
-            const long long idx = (long long)(code >> 3), row = idx / n;
-            return fail(FJOFC_EINVAL, "delta_new: object %lld, modality %lld, entry %lld %s",
-                        row / m, row % m, idx % n, offence_name((int)(code & 7)));
-        }
-    }
+    return oos_run(ctx, X_in, m, n, d, wmat, delta_new, k, Y, iters, tol, target, stress_out,
+                   iters_out, sync, stream, false);
+}
 
-    std::vector<double> W((size_t)m * m), Li((size_t)m * m);
-    wmod(m, n, wmat, W.data());
-    if (!invert(m, W.data(), Li.data()))
-        return fail(FJOFC_ESINGULAR, "eq:modW matrix is singular");
-
-    TriGeom g{};
-    g.n = n;
-    g.m = m;
-    g.npad = (n + 255) / 256 * 256;
-    Carve cv;
-    const size_t oX = cv.take<float>((size_t)m * d * g.npad);
-    const size_t oC = cv.take<double>((size_t)m * d);
-    const size_t oL = cv.take<double>((size_t)m * m);
-    const size_t oW = cv.take<double>((size_t)m * m);
-    rc = ensure_ws(ctx, cv.off);
-    if (rc) return rc;
-    char *b = static_cast<char *>(ctx->ws);
-    float *Xs = reinterpret_cast<float *>(b + oX);
-    double *colsum = reinterpret_cast<double *>(b + oC);
-    double *dLi = reinterpret_cast<double *>(b + oL);
-    double *dW = reinterpret_cast<double *>(b + oW);
-    HIP_TRY(hipMemcpyAsync(dLi, Li.data(), sizeof(double) * m * m, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(dW, wmat, sizeof(double) * m * m, hipMemcpyHostToDevice, s));
-    HIP_TRY(launch_to_soa(g, d, X_in, Xs, s));
-
-    OOSArgs a;
-    a.Xs = Xs;
-    a.m = m;
-    a.n = n;
-    a.npad = g.npad;
-    a.D = d;
-    a.dnew = delta_new;
-    a.k = k;
-    a.Y = Y;
-    a.Linv = dLi;
-    a.wmat = dW;
-    a.target = target;
-    a.stress_out = stress_out;
-    a.iters_out = iters_out;
-    a.tol = tol;
-    a.iters = iters;
-    a.ob = 0;  // the default objects per workgroup
-    a.vec4 = (n % 4 == 0 && (reinterpret_cast<uintptr_t>(delta_new) & 15) == 0 &&
-              !std::getenv("FJOFC_OOS_SCALAR")) ? 1 : 0;
-    {
-        Timed tm(ctx, K_OOS, 4.0 * (double)k * m * n * (iters + 1), s);
-        HIP_TRY(launch_oos(a, colsum, s));
-    }
-    if (sync) HIP_TRY(hipStreamSynchronize(s));
-    return FJOFC_OK;
+int fjofc_oos_noalloc(fjofc_ctx *ctx, const float *X_in, int m, int n, int d,
+                      const double *wmat, const float *delta_new, int k, float *Y,
+                      int iters, double tol, const double *target, double *stress_out,
+                      int *iters_out, int sync, void *stream) {
+    return oos_run(ctx, X_in, m, n, d, wmat, delta_new, k, Y, iters, tol, target, stress_out,
+                   iters_out, sync, stream, true);
 }
 
 int fjofc_oos_nearest_start(fjofc_ctx *ctx, const float *X_in, int m, int n, int d,

@@ -30,7 +30,7 @@ EXPORTS = ["fjofc_create", "fjofc_destroy", "fjofc_last_error", "fjofc_strerror"
            "fjofc_mlp_get_grads", "fjofc_mlp_adam", "fjofc_mlp_features",
            "fjofc_mlp_predict_start", "fjofc_oos_nearest_start", "fjofc_embed_relaxed",
            "fjofc_init_cmds", "fjofc_mlp_loss", "fjofc_mlp_feature_stats",
-           "fjofc_oos_consensus", "fjofc_validate_delta"]
+           "fjofc_oos_consensus", "fjofc_validate_delta", "fjofc_oos_noalloc"]
 
 
 class FjofcResult(C.Structure):
@@ -103,6 +103,7 @@ def lib():
                                    C.POINTER(FjofcResult), vp]
         L.fjofc_oos.argtypes = [vp, vp, ip, ip, ip, C.POINTER(dp), vp, ip, vp,
                                 ip, dp, vp, vp, vp, ip, vp]
+        L.fjofc_oos_noalloc.argtypes = L.fjofc_oos.argtypes
         L.fjofc_batch_create.argtypes = [vp, C.POINTER(FjofcProblem), ip, C.POINTER(vp)]
         L.fjofc_batch_run.argtypes = [vp, ip, dp, ip, ip, C.POINTER(FjofcResult), vp]
         L.fjofc_batch_destroy.argtypes = [vp]
@@ -248,6 +249,21 @@ def fjofc_oos(ctx: Context, X_in, wmat, delta_new, Y, iters: int,
     """Out-of-sample embedding.  X_in: (m n) x d; delta_new: k x m x n;
     Y: k x m x d (starts in, results out); target / stress_out (float64, k)
     and iters_out (int32, k) are optional CUDA tensors."""
+    _oos_call(lib().fjofc_oos, ctx, X_in, wmat, delta_new, Y, iters, tol, target, stress_out,
+              iters_out, sync, stream)
+
+
+def fjofc_oos_noalloc(ctx: Context, X_in, wmat, delta_new, Y, iters: int,
+                      tol: float = 0.0, target=None, stress_out=None, iters_out=None,
+                      sync: bool = True, stream=None):
+    """fjofc_oos without any device allocation (the library's per-GPU
+    scratch array; m <= 8 and a bounded m d n)."""
+    _oos_call(lib().fjofc_oos_noalloc, ctx, X_in, wmat, delta_new, Y, iters, tol, target,
+              stress_out, iters_out, sync, stream)
+
+
+def _oos_call(fn, ctx, X_in, wmat, delta_new, Y, iters, tol, target, stress_out, iters_out,
+              sync, stream):
     import torch
     k, m, n = (int(s) for s in delta_new.shape)
     d = int(X_in.shape[1])
@@ -255,10 +271,10 @@ def fjofc_oos(ctx: Context, X_in, wmat, delta_new, Y, iters: int,
     tp = _dev_ptr(target, torch.float64, "target") if target is not None else None
     sp = _dev_ptr(stress_out, torch.float64, "stress_out") if stress_out is not None else None
     itp = _dev_ptr(iters_out, torch.int32, "iters_out") if iters_out is not None else None
-    _check(lib().fjofc_oos(ctx.handle, _dev_ptr(X_in, torch.float32, "X_in"), m, n, d,
-                           wp, _dev_ptr(delta_new, torch.float32, "delta_new"), k,
-                           _dev_ptr(Y, torch.float32, "Y"), int(iters), float(tol),
-                           tp, sp, itp, 1 if sync else 0, _stream_ptr(stream)))
+    _check(fn(ctx.handle, _dev_ptr(X_in, torch.float32, "X_in"), m, n, d,
+              wp, _dev_ptr(delta_new, torch.float32, "delta_new"), k,
+              _dev_ptr(Y, torch.float32, "Y"), int(iters), float(tol),
+              tp, sp, itp, 1 if sync else 0, _stream_ptr(stream)))
 
 
 def fjofc_oos_nearest_start(ctx: Context, X_in, delta_new, Y, stream=None):
