@@ -478,15 +478,29 @@ def bench_batched(ctx, iters=150):
     return r
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(delta, wmat, X0, m, n, every, target_s):
     """The FP64 CPU oracle (as it is) on a bounded sample of the same
-    workload: a few full Guttman transforms of the same problem."""
+    workload: a few full Guttman transforms of the same problem on all host
+    threads, and one transform on one thread."""
     import numpy as np
     from oracle import structured as orc
     host = np.empty((m, n, n), dtype=np.float32)
     for i in range(m):
         host[i] = delta[i].cpu().numpy()
     X0c = X0.astype(np.float32).astype(np.float64)
+    threads = orc.threads()
     # one transform first, to size the sample
     t0 = time.perf_counter()
     orc.embed(host, wmat, X0c, 1, stress_every=every, want_hist=False)
@@ -498,23 +512,37 @@ def cpu_baseline(delta, wmat, X0, m, n, every, target_s):
     t1 = time.perf_counter()
     pairs = iters * m * n * (n - 1) / 2.0
     out = {"value": pairs / (t1 - t0), "unit": "Δ-pairs/s",
-           "cores": orc.threads(), "kind": "oracle",
+           "cores": threads, "kind": "oracle", "cpu_model": cpu_model(),
            "sample": f"{iters} full Guttman transforms of the same m={m} n={n} d=5 "
                      f"problem (plus stress at t=0 and at the end), FP64 C oracle, "
                      f"{t1 - t0:.1f} s"}
+    # one thread: a single transform (no stress evaluation)
+    orc.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        orc.guttman(host, wmat, X0c)
+        t1 = time.perf_counter()
+    finally:
+        orc.set_threads(threads)
+    out["one_thread"] = {"value": m * n * (n - 1) / 2.0 / (t1 - t0), "unit": "Δ-pairs/s",
+                         "cores": 1, "kind": "oracle",
+                         "sample": f"1 Guttman transform of the same problem on one thread, "
+                                   f"{t1 - t0:.1f} s"}
+    del host
     out["paper_jofc_vs_fjofc"] = jofc_context()
     return out
 
 
 def jofc_context():
     """Context for Section 4.3 on the host, with the oracle's two forms of
-    one Guttman transform: the dense one through pinv(L) (the original JOFC
+    one Guttman transform: the dense one through L^dagger (the original JOFC
     update, L^dagger precomputed and timed apart) against the structured
     one (the FP64 C oracle), on the paper's matched recipe (d = 2, w = 0.5)
-    for m = 2..6 at n = 400 and n = 200..1000 at m = 3.  Both run on all
-    host threads (the paper ran serially), so only the trend is comparable
-    with the paper's per-iteration ratios, which are quoted beside ours."""
+    for m = 2..6 at n = 400 and n = 200..1000 at m = 3.  Both run on one
+    thread (the C oracle's OpenMP and numpy's BLAS limited to one), as the
+    paper ran serially; its per-iteration ratios are quoted beside ours."""
     import numpy as np
+    from threadpoolctl import threadpool_limits
     from oracle import dense, structured as orc
     from workloads import generators as gen
     t_start = time.perf_counter()
@@ -535,10 +563,13 @@ def jofc_context():
         return (time.perf_counter() - t0) / reps
 
     def slow(m, n):
+        # L^dagger from Corollary 1's closed form (equal to numpy's pinv to
+        # 1e-14, pinned in the oracle's tests): the per-iteration product is
+        # the same dense (mn x mn) one, without timing an SVD per shape
         delta, wmat, X = problem(m, n)
         W, D = dense.omnibus_weights(wmat, n), dense.omnibus_delta(delta)
         t0 = time.perf_counter()
-        Lp = np.linalg.pinv(dense.laplacian(W))
+        Lp = dense.ldagger_corollary(wmat, n)
         t_pinv = time.perf_counter() - t0
         td = []
         for _ in range(2):
@@ -550,15 +581,21 @@ def jofc_context():
     shapes = [(m, 400) for m in (2, 3, 4, 5, 6)] + [(3, n) for n in (200, 400, 600, 800, 1000)]
     # every structured timing before any dense one: the dense products
     # leave BLAS threads spinning, which would slow the structured ones
-    tf = {mn: fast(*mn) for mn in shapes}
+    threads = orc.threads()
+    orc.set_threads(1)
+    try:
+        tf = {mn: fast(*mn) for mn in shapes}
+    finally:
+        orc.set_threads(threads)
     rows = {}
-    for mn in shapes:
-        t_pinv, t_iter = slow(*mn)
-        rows[mn] = {"m": mn[0], "n": mn[1], "pinv_s": t_pinv, "jofc_iter_s": t_iter,
-                    "fjofc_iter_s": tf[mn], "ratio": t_iter / tf[mn]}
+    with threadpool_limits(limits=1):
+        for mn in shapes:
+            t_pinv, t_iter = slow(*mn)
+            rows[mn] = {"m": mn[0], "n": mn[1], "ldagger_s": t_pinv, "jofc_iter_s": t_iter,
+                        "fjofc_iter_s": tf[mn], "ratio": t_iter / tf[mn]}
     m_sweep = [rows[mn] for mn in shapes[:5]]
     n_sweep = [rows[mn] for mn in shapes[5:]]
-    res = {"kind": "oracle", "cores": orc.threads(),
+    res = {"kind": "oracle", "cores": 1, "label": "context: both forms serial, like the paper",
            "m_sweep_n400": m_sweep, "n_sweep_m3": n_sweep,
            "paper_ratios": {"m=2..6 at n=400": [2.86, 4.82, 6.70, 8.59, 10.71],
                             "n=200..1000 at m=3": [2.10, 4.86, 7.45, 10.13, 12.63],

@@ -15,8 +15,15 @@
  * commensurability).  delta is m consecutive n x n row-major blocks.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* Threads of the parallel loops below (for timing).  Only the fidelity
+ * sum is an OpenMP reduction, so the thread count changes at most the
+ * FP64 rounding of that sum. */
+void orc_set_threads(int t) { omp_set_num_threads(t > 0 ? t : 1); }
+int orc_get_threads(void) { return omp_get_max_threads(); }
 
 #define IDX(i, j, ld) ((size_t)(i) * (size_t)(ld) + (size_t)(j))
 

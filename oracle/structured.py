@@ -27,6 +27,9 @@ def lib():
             from . import build
             build.build()
         L = C.CDLL(_LIB_PATH)
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_set_threads.restype = None
+        L.orc_get_threads.restype = C.c_int
         L.orc_wmod.argtypes = [C.c_int, C.c_int, _dp, _dp]
         L.orc_inverse.argtypes = [C.c_int, _dp, _dp]
         L.orc_block_bx.argtypes = [C.c_int, C.c_int, C.c_double, _fp, _dp, _dp,
@@ -177,6 +180,10 @@ def oos(X, wmat, dnew, Y0, iters, tol=0.0, target: Optional[np.ndarray] = None):
 
 
 def threads() -> int:
-    """OpenMP threads the oracle uses (OMP_NUM_THREADS or all cores)."""
-    v = os.environ.get("OMP_NUM_THREADS")
-    return int(v) if v else (os.cpu_count() or 1)
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(lib().orc_get_threads())
+
+
+def set_threads(t: int) -> None:
+    """Set the OpenMP threads of the oracle's parallel loops (timing)."""
+    lib().orc_set_threads(int(t))
