@@ -29,16 +29,23 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_insample_stream_m3_n20000
 KERNEL_SRC = os.path.join(ROOT, "paper_1502_03391_amd", "csrc", "insample.hip")
 OOS_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_oos_m2_n10000_d5.json")
 OOS_SRC = os.path.join(ROOT, "paper_1502_03391_amd", "csrc", "oos.hip")
+BATCHED_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_batched_512_uneven.json")
+# the batch's kernels and its launch plan
+BATCHED_SRC = (KERNEL_SRC, os.path.join(ROOT, "paper_1502_03391_amd", "csrc", "host.cpp"))
 
 
 def kernel_hash(src=KERNEL_SRC) -> str:
-    with open(src, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in ((src,) if isinstance(src, str) else src):
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
-def load_traffic(path=TRAFFIC_FILE, src=KERNEL_SRC):
-    """HBM bytes per launch of a kernel from committed rocprofv3 counter
-    runs, or None when absent or taken on a different kernel source."""
+def load_traffic(path=TRAFFIC_FILE, src=KERNEL_SRC, key="bytes_per_launch"):
+    """HBM bytes per launch of a kernel (or per unit `key` names) from
+    committed rocprofv3 counter runs, or None when absent or taken on a
+    different kernel source."""
     try:
         with open(path) as f:
             t = json.load(f)
@@ -46,7 +53,7 @@ def load_traffic(path=TRAFFIC_FILE, src=KERNEL_SRC):
         return None
     if t.get("kernel_sha") != kernel_hash(src):
         return None
-    return t.get("bytes_per_launch")
+    return t.get(key)
 
 
 def parse():
@@ -65,6 +72,13 @@ def parse():
     ap.add_argument("--extras", default="relaxed,init,paper,early,oos,batched,warmstart",
                     help="comma list of extra workloads to measure after the main one "
                          "(relaxed, init, paper, early, oos, batched, warmstart) or 'none'")
+    ap.add_argument("--only-extras", action="store_true",
+                    help="skip the main workload and print only the extras' JSON "
+                         "(for profiled runs of one extra workload)")
+    ap.add_argument("--batched-iters", type=int, default=150,
+                    help="transforms per batched run (default: the workload's 150)")
+    ap.add_argument("--batched-launches", default="lockstep,persistent",
+                    help="batched launches to time: lockstep (reported), persistent")
     return ap.parse_args()
 
 
@@ -81,6 +95,20 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    extras = [e for e in args.extras.split(",") if e and e != "none"]
+    if args.calib_copy:
+        a = torch.empty(2 << 30, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    if args.only_extras:
+        ctx = fjofc.Context(0)
+        out = {"extra": {}}
+        independent_extras(ctx, extras, out, args)
+        ctx.close()
+        print(json.dumps(out), flush=True)
+        return
     spec = gen.config1_spec()
     m, n, d, iters, every = spec.m, spec.n, spec.d, spec.iters, spec.stress_every
     if args.iters is not None:
@@ -92,13 +120,6 @@ def main():
     X = torch.empty_like(X0d)
     torch.cuda.synchronize()
     print(f"[bench] inputs ready: m={m} n={n} d={d}", file=sys.stderr, flush=True)
-
-    if args.calib_copy:
-        a = torch.empty(2 << 30, dtype=torch.uint8, device=dev)
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
 
     ctx = fjofc.Context(0)
 
@@ -160,7 +181,6 @@ def main():
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(delta, wmat, X0, m, n, every, args.cpu_seconds)
-    extras = [e for e in args.extras.split(",") if e and e != "none"]
     out["extra"] = {}
     if "relaxed" in extras:
         out["extra"]["relaxed"] = bench_relaxed(ctx, delta, wmat, X0d, res["stress"], iters,
@@ -169,6 +189,13 @@ def main():
         out["extra"]["init"] = bench_init(ctx, delta, wmat, res["stress"], iters, every)
     del delta, X, X0d
     torch.cuda.empty_cache()
+    independent_extras(ctx, extras, out, args)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def independent_extras(ctx, extras, out, args):
+    """The extra workloads that build their own inputs."""
     if "paper" in extras:
         out["extra"]["paper"] = bench_paper_shape(ctx)
     if "early" in extras:
@@ -176,11 +203,10 @@ def main():
     if "oos" in extras:
         out["extra"]["oos"] = bench_oos(ctx)
     if "batched" in extras:
-        out["extra"]["batched"] = bench_batched(ctx)
+        out["extra"]["batched"] = bench_batched(
+            ctx, args.batched_iters, [x for x in args.batched_launches.split(",") if x])
     if "warmstart" in extras:
         out["extra"]["warmstart"] = bench_warmstart(ctx)
-    ctx.close()
-    print(json.dumps(out), flush=True)
 
 
 def bench_oos(ctx):
@@ -284,10 +310,18 @@ def bench_init(ctx, delta, wmat, random_final, iters, every, init_iters=20):
     X = torch.empty((m * n, d), device=delta[0].device)
     fjofc.fjofc_init_cmds(ctx, delta, X, iters=2)  # warm-up
     torch.cuda.synchronize()
+    fjofc.fjofc_profile_enable(ctx, True)
     t0 = time.perf_counter()
     eig = fjofc.fjofc_init_cmds(ctx, delta, X, iters=init_iters)
     torch.cuda.synchronize()
     t_init = time.perf_counter() - t0
+    prof = fjofc.fjofc_profile_read(ctx)
+    fjofc.fjofc_profile_enable(ctx, False)
+    # product passes: every Delta_i read once per pass (full rows), all
+    # m + 1 problems formed from those reads
+    pass_ms = prof["init_ms"] / max(1, prof["init_launches"])
+    pass_bytes = prof["init_bytes"] / max(1, prof["init_launches"])
+    pass_gbs = pass_bytes / (pass_ms * 1e-3) / 1e9
     s0 = fjofc.fjofc_stress(ctx, delta, wmat, X)["stress"]
     target = random_final * (1.0 + 1e-4)
     torch.cuda.synchronize()
@@ -297,12 +331,19 @@ def bench_init(ctx, delta, wmat, random_final, iters, every, init_iters=20):
     torch.cuda.synchronize()
     t_embed = time.perf_counter() - t0
     out = {"workload": "insample_m3_n20000_d5_paper_start", "init_iters": init_iters,
-           "init_seconds": t_init, "start_stress": s0, "top_ritz_mean": eig[0].tolist(),
+           "init_seconds": t_init, "product_passes": prof["init_launches"],
+           "pass_ms": pass_ms, "pass_bytes": pass_bytes, "pass_hbm_gbs": pass_gbs,
+           "pass_hbm_frac": pass_gbs / PEAK_HBM_GBS,
+           "pass_triangle_frac": 0.5 * pass_gbs / PEAK_HBM_GBS,
+           "products_seconds": prof["init_ms"] * 1e-3,
+           "start_stress": s0, "top_ritz_mean": eig[0].tolist(),
            "target_stress": target, "transforms_to_target": r["iters_run"],
            "reached": bool(r["converged"]), "embed_seconds": t_embed,
            "random_start_transforms": iters,
            "total_seconds": t_init + t_embed}
-    print(f"[bench] paper start: init {t_init:.3f} s, {r['iters_run']} transforms "
+    print(f"[bench] paper start: init {t_init:.3f} s ({prof['init_launches']} passes of "
+          f"{pass_ms:.3f} ms, {pass_gbs:.0f} GB/s)", file=sys.stderr, flush=True)
+    print(f"[bench] paper start: {r['iters_run']} transforms "
           f"({t_embed:.3f} s) to the random start's {iters}-transform stress",
           file=sys.stderr, flush=True)
     return out
@@ -430,9 +471,11 @@ def bench_warmstart(ctx):
     return r
 
 
-def bench_batched(ctx, iters=150):
+def bench_batched(ctx, iters=150, launches=("lockstep", "persistent")):
     """512 independent problems, m ~ U{2,3,4}, n ~ U[64,2048], d ~ U{2,3,5},
-    150 transforms each, replayed from one captured HIP graph."""
+    150 transforms each, replayed from a captured HIP graph: the lockstep
+    launches (the library's default and the reported time) and the one
+    persistent launch, which must give bitwise the same results."""
     import numpy as np
     import torch
     from paper_1502_03391_amd import fjofc
@@ -450,29 +493,50 @@ def bench_batched(ctx, iters=150):
         pairs += sp.m * sp.n * (sp.n - 1) / 2.0
     torch.cuda.synchronize()
     print(f"[bench] batched inputs ready: {len(specs)} problems", file=sys.stderr, flush=True)
-    b = fjofc.Batch(ctx, probs)
 
     def reset():
         for (_, _, X), X0 in zip(probs, X0s):
             X.copy_(X0)
         torch.cuda.synchronize()
 
-    reset()
-    b.run(iters, stress_every=iters, want_results=False)
-    torch.cuda.synchronize()
-    times = []
-    for _ in range(3):
+    def timed(launch):
+        b = fjofc.Batch(ctx, probs, launch=launch)
         reset()
-        t0 = time.perf_counter()
-        res = b.run(iters, stress_every=iters)
-        t1 = time.perf_counter()
-        times.append(t1 - t0)
-    sec = min(times)
-    b.close()
+        b.run(iters, stress_every=iters, want_results=False)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(3):
+            reset()
+            t0 = time.perf_counter()
+            res = b.run(iters, stress_every=iters)
+            t1 = time.perf_counter()
+            times.append(t1 - t0)
+        out = [X.clone() for _, _, X in probs]
+        b.close()
+        return min(times), res, out
+
+    runs = {la: timed(la) for la in launches}
+    first = runs[launches[0]]
+    sec, res = first[0], first[1]
+    hbm = load_traffic(BATCHED_TRAFFIC_FILE, BATCHED_SRC, "bytes_per_sweep")
     r = {"workload": "batched_512_uneven", "problems": len(specs), "iters": iters,
-         "pairs_per_sweep": pairs, "seconds": sec, "pairs_per_s": pairs * iters / sec,
+         "launch": launches[0], "pairs_per_sweep": pairs,
+         "algorithmic_bytes_per_sweep": 4.0 * pairs,
+         "hbm_bytes_per_sweep": hbm,
+         "seconds": sec, "pairs_per_s": pairs * iters / sec,
          "algorithmic_gbs": 4.0 * pairs * iters / sec / 1e9,
          "mean_stress_norm": float(np.mean([x["stress_norm"] for x in res]))}
+    if hbm is not None:
+        r["hbm_gbs"] = hbm * iters / sec / 1e9
+    if "persistent" in runs and launches[0] != "persistent":
+        sec_p, res_p, Xp = runs["persistent"]
+        r["persistent_seconds"] = sec_p
+        r["persistent_equals_lockstep"] = (
+            all(torch.equal(a, c) for a, c in zip(Xp, first[2])) and res == res_p)
+    print(f"[bench] batched: " + ", ".join(f"{la} {runs[la][0]:.4f} s" for la in launches)
+          + (f" (bitwise equal: {r['persistent_equals_lockstep']})"
+             if "persistent_equals_lockstep" in r else ""), file=sys.stderr, flush=True)
+    del runs, first
     del probs
     torch.cuda.empty_cache()
     return r

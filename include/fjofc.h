@@ -36,12 +36,17 @@
  *
  * Tuning overrides (environment variables, read when a problem is planned
  * or launched; none changes what is computed beyond FP32 summation order):
- *  - FJOFC_TUNE_TABLE  path of the stream tile table (default:
- *                      tune_gfx950.txt next to the library); a d with no
- *                      rows uses those of the nearest tabulated d;
+ *  - FJOFC_TUNE_TABLE  path of the stream tile cache (default:
+ *                      tune_cache.txt next to the library), read once per
+ *                      process: lines "arch d n_max tile_height variant";
+ *                      only the device architecture's rows apply, and a d
+ *                      with no rows uses those of the nearest tabulated d;
  *  - FJOFC_TILE        "th:variant" forces the in-sample tile height and
  *                      kernel variant (the height is rounded up to whole
- *                      8-row groups per wavefront);
+ *                      8-row groups per wavefront); a comma-separated list
+ *                      of "d:n_lo:n_hi:th:variant" forces it only for the
+ *                      problems of that d with n_lo <= n <= n_hi (the
+ *                      autotuner's per-bucket candidates);
  *  - FJOFC_OOS_OB      1..4 objects per out-of-sample workgroup (default 4);
  *  - FJOFC_OOS_SCALAR  any value: the out-of-sample stream uses 4-byte
  *                      loads even when n % 4 == 0;
@@ -161,8 +166,10 @@ int fjofc_embed_relaxed(fjofc_ctx *ctx, const float *const *delta, int m,
  * cMDS of A: the d largest eigenpairs (lambda, u) of
  * P = -1/2 (I - J/n)(A o A)(I - J/n); X = [u_1..u_d] diag(max(lambda,0))^(1/2)
  * (centred).  They are computed by `iters` steps of subspace iteration on
- * a block of K >= max(2d, d + 3) vectors (each step streams the m Delta_i
- * once for the mean and once for its own Delta_i), then Rayleigh-Ritz.
+ * a block of K >= max(2d, d + 3) vectors per matrix, then Rayleigh-Ritz.
+ * The m + 1 iterations step together: for m <= 4 each step reads every
+ * Delta_i once (full rows) and forms the mean's and all m per-matrix
+ * products from those reads; for m > 4 the mean takes a pass of its own.
  *   delta, m, n, d  as for fjofc_embed (d <= FJOFC_MAX_D).
  *   X               device (m*n) x d FP32, written.
  *   iters           subspace-iteration steps per matrix, 1..10000.
@@ -249,9 +256,9 @@ int fjofc_oos_nearest_start(fjofc_ctx *ctx, const float *X_in, int m, int n,
 
 /*
  * Batched in-sample fJOFC: many independent problems of different m, n, d
- * advanced in lockstep (one stream launch per kernel variant and one
- * combine launch per transform), the whole loop captured once into a HIP
- * graph on a library-owned stream and replayed.  Each problem keeps its own
+ * advanced together (in lockstep launches, or in one persistent launch:
+ * fjofc_batch_set_launch), the whole loop captured once into a HIP graph on
+ * a library-owned stream and replayed.  Each problem keeps its own
  * stop rule (a stopped problem's tiles become no-ops).  Tile shapes come
  * from the autotuned table, per (d, n).
  */
@@ -277,6 +284,32 @@ int fjofc_batch_create(fjofc_ctx *ctx, const fjofc_problem *probs, int count,
  * when given the call synchronises `stream`.                               */
 int fjofc_batch_run(fjofc_batch *b, int iters, double tol, int tol_mode,
                     int stress_every, fjofc_result *res, void *stream);
+/* The in-sample stream tile the library plans for an (n, d) problem on
+ * ctx's device: tile height (rows, after rounding to whole row groups) and
+ * kernel variant, from FJOFC_TILE, the tuning cache or the default.  Lets
+ * a caller check which cache row applies.  FJOFC_EINVAL for n < 2 or d
+ * outside [1, FJOFC_MAX_D] or NULL outputs.                                */
+int fjofc_tile_choice(fjofc_ctx *ctx, int n, int d, int *tile_height, int *variant);
+
+/* How fjofc_batch_run advances the batch (the paper's parallel structure,
+ * Remarks rem:pargut and rem:parfjofc: the tiles of every problem and
+ * transform are independent given the current configurations).
+ *   FJOFC_LAUNCH_LOCKSTEP (the default): per transform one stream launch per
+ *     kernel variant and one reduce/finalize launch per group, in one graph.
+ *   FJOFC_LAUNCH_PERSISTENT: one persistent launch per run (in the graph),
+ *     workgroups pulling (problem, transform, tile group / reduce /
+ *     finalize group) tasks from a device queue and waiting, bounded, on
+ *     per-problem progress counters; the grid is the co-resident workgroup
+ *     count.  A wait that times out (5000 ms of wall clock by default,
+ *     FJOFC_BATCH_TIMEOUT_MS) ends the launch and the run returns
+ *     FJOFC_EHIP.  Both launches run the same tiles and sums: results are
+ *     bitwise equal.
+ * Returns FJOFC_EINVAL for an unknown value, or for the persistent launch
+ * when a problem's tile shape has no persistent variant.  A change of launch
+ * discards the captured graph (the next run captures again).              */
+#define FJOFC_LAUNCH_LOCKSTEP 0
+#define FJOFC_LAUNCH_PERSISTENT 1
+int fjofc_batch_set_launch(fjofc_batch *b, int launch);
 void fjofc_batch_destroy(fjofc_batch *b);
 /* create + run + destroy.                                                  */
 int fjofc_embed_batched(fjofc_ctx *ctx, const fjofc_problem *probs, int count,
@@ -374,8 +407,8 @@ int fjofc_validate_delta(fjofc_ctx *ctx, const float *delta, int n, long long *w
 
 /*
  * Per-kernel timing (tracing aid).  While enabled, every kernel launch of
- * fjofc_embed / fjofc_stress / fjofc_oos is bracketed by HIP events on the
- * caller's stream; fjofc_profile_read synchronises and returns the summed
+ * fjofc_embed / fjofc_stress / fjofc_oos (and each product pass of
+ * fjofc_init_cmds) is bracketed by HIP events on the caller's stream; fjofc_profile_read synchronises and returns the summed
  * durations per kernel kind together with the algorithmic bytes the
  * in-sample stream launches read (4 bytes per unordered pair of every
  * dissimilarity block, i.e. one read of each strict-upper-triangle entry)
@@ -400,6 +433,9 @@ typedef struct {
     int batch_launches;      /* whole batched graph replays                */
     double batch_ms;
     double batch_bytes;      /* 4 B per pair per transform, all problems   */
+    int init_launches;       /* fjofc_init_cmds product passes             */
+    double init_ms;
+    double init_bytes;       /* 4 B per entry of every Delta_i read        */
 } fjofc_profile;
 
 int fjofc_profile_enable(fjofc_ctx *ctx, int on);

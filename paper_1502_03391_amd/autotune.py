@@ -1,12 +1,25 @@
 """Autotuner of the in-sample stream kernel's tile shape and variant.
 
-For each embedding dimension d and n-bucket it times every candidate
-(tile height, kernel variant) on the GPU through the public API (the
-library's per-launch HIP-event timing, with FJOFC_TILE forcing the
-candidate) and writes the fastest per bucket to ``tune_gfx950.txt`` next to
-libfjofc.so, which the library reads on first use (``FJOFC_TUNE_TABLE``
-overrides the path).  Cost per candidate = stream + finalize + reduce time
-per transform, averaged over a few transforms after a warm-up run.
+Writes the tile cache the library reads (``tune_cache.txt`` next to
+libfjofc.so, or ``FJOFC_TUNE_TABLE``): one row per (architecture, d,
+n-bucket) giving the tile height and kernel variant.  Every candidate is
+timed on the GPU through the public API, with FJOFC_TILE forcing it.  Two
+objectives, by bucket:
+
+* buckets up to n = 2048, the range of the batched workload (many small,
+  uneven problems: m ~ U{2,3,4}, n ~ U[64, 2048], d ~ U{2,3,5}): the wall
+  time of ``iters`` transforms of that whole batch, replayed from its
+  captured graph, with the candidate forced on the problems of the bucket's
+  d and n range only.  Buckets are tuned one after another, earlier
+  decisions of the run staying in force, so a candidate is judged with the
+  launches it shares with the rest of the batch;
+* larger buckets: one m = 3 problem at a representative n (the single
+  large problem is the workload there): stream + finalize + reduce time per
+  transform from the library's HIP-event timing.
+
+A run replaces the rows of the (arch, d, n_max) keys it tunes and keeps
+every other row of the existing cache, so ``--buckets``/``--dims`` refresh a
+part of it.
 
 Run on the GPU:  python -m paper_1502_03391_amd.autotune [--dims 2,3,5]
 """
@@ -18,24 +31,55 @@ import sys
 import time
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-TABLE = os.path.join(HERE, "tune_gfx950.txt")
+CACHE = os.path.join(HERE, "tune_cache.txt")
 
 # variant numbers as in the library: 0 = (4 cols/lane, 8-row groups,
 # double-buffered), 1 = (4, 8, single), 2 = (8, 4, single), 3 = (8, 8, single);
 # 4 and 5 are variant 1 with 4 x 1 and 2 x 2 wavefronts sharing a tile
 CANDIDATES = [(64, 1), (96, 1), (128, 1), (160, 1), (192, 1), (256, 1), (128, 0), (256, 0),
               (64, 2), (128, 2), (256, 2), (128, 3), (256, 3), (512, 3),
-              (256, 4), (384, 4), (512, 4), (128, 5), (256, 5), (384, 5)]
+              (64, 4), (96, 4), (128, 4), (256, 4), (384, 4), (512, 4),
+              (64, 5), (128, 5), (256, 5), (384, 5)]
 BUCKETS = [128, 256, 512, 1024, 2048, 4096, 8192, 16384, 1 << 30]
+BATCH_MAX_N = 2048  # buckets up to here take the batch objective
 
 
 def _rep_n(nmax: int) -> int:
     return {1 << 30: 20000}.get(nmax, nmax - nmax // 8)
 
 
-def _time_candidate(ctx, fjofc, delta, wmat, X0, th, var, iters):
+def _bucket_lo(nmax: int) -> int:
+    i = BUCKETS.index(nmax)
+    return BUCKETS[i - 1] + 1 if i else 2
+
+
+def read_cache(path: str):
+    """{(arch, d, n_max): (th, variant, comment)} of an existing cache."""
+    rows = {}
+    if not os.path.exists(path):
+        return rows
+    with open(path) as f:
+        for line in f:
+            body, _, comment = line.partition("#")
+            p = body.split()
+            if len(p) == 5:
+                rows[(p[0], int(p[1]), int(p[2]))] = (int(p[3]), int(p[4]), comment.strip())
+    return rows
+
+
+def write_cache(path: str, rows, device_name: str):
+    with open(path, "w") as f:
+        f.write("# fJOFC in-sample stream tile cache, written by autotune.py\n")
+        f.write(f"# last run {time.strftime('%Y-%m-%d')} on {device_name}\n")
+        f.write("# arch d n_max tile_height variant   # objective and its time\n")
+        for (arch, d, nmax) in sorted(rows):
+            th, var, comment = rows[(arch, d, nmax)]
+            f.write(f"{arch} {d} {nmax} {th} {var}   # {comment}\n")
+
+
+def _single_cost(ctx, fjofc, delta, wmat, X0, iters):
+    """Stream + finalize + reduce ms per transform of one problem."""
     import torch
-    os.environ["FJOFC_TILE"] = f"{th}:{var}"
     X = X0.clone()
     fjofc.fjofc_embed(ctx, delta, wmat, X, 2, stress_every=iters)
     torch.cuda.synchronize()
@@ -51,15 +95,67 @@ def _time_candidate(ctx, fjofc, delta, wmat, X0, th, var, iters):
     return best
 
 
+class _BatchObjective:
+    """The uneven batch, built once; cost = wall ms per transform of the
+    whole batch replayed from its graph."""
+
+    def __init__(self, ctx, count, iters):
+        import numpy as np
+        import torch
+        from paper_1502_03391_amd import fjofc
+        sys.path.insert(0, os.path.dirname(HERE))
+        from workloads import generators as gen
+        dev = torch.device("cuda:0")
+        self.ctx, self.iters, self.fjofc = ctx, iters, fjofc
+        self.specs = gen.batched_specs(count)
+        self.probs, self.X0 = [], []
+        for sp in self.specs:
+            views, _, X0 = gen.instance_views(sp)
+            X0d = torch.from_numpy(X0.astype(np.float32)).to(dev)
+            self.probs.append(([gen.pairwise_dist_torch(Y, dev) for Y in views],
+                               gen.uniform_wmat(sp.m, 0.5), X0d.clone()))
+            self.X0.append(X0d)
+        torch.cuda.synchronize()
+
+    def members(self, d, lo, hi):
+        return [sp for sp in self.specs if sp.d == d and lo <= sp.n <= hi]
+
+    def cost(self):
+        import torch
+        b = self.fjofc.Batch(self.ctx, self.probs)
+        best = None
+        for rep in range(3):
+            for (_, _, X), X0 in zip(self.probs, self.X0):
+                X.copy_(X0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            b.run(self.iters, stress_every=self.iters, want_results=False)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) * 1e3 / self.iters
+            if rep:  # the first run captures the graph
+                best = t if best is None else min(best, t)
+        b.close()
+        return best
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description="tune the in-sample stream kernel")
     ap.add_argument("--dims", default="2,3,5")
-    ap.add_argument("--m", type=int, default=3)
-    ap.add_argument("--out", default=TABLE)
     ap.add_argument("--buckets", default=None,
-                    help="comma-separated n_max values to tune (default: all)")
+                    help="comma-separated n_max values to tune (default: all); "
+                         "other rows of the cache are kept")
+    ap.add_argument("--m", type=int, default=3, help="m of the single-problem objective")
+    ap.add_argument("--batch-count", type=int, default=512,
+                    help="problems of the batch objective (default: the workload's 512)")
+    ap.add_argument("--iters", type=int, default=30,
+                    help="transforms per timed batch run")
+    ap.add_argument("--out", default=CACHE)
     args = ap.parse_args(argv)
     buckets = BUCKETS if not args.buckets else [int(x) for x in args.buckets.split(",")]
+    for nmax in buckets:
+        if nmax not in BUCKETS:
+            ap.error(f"unknown bucket {nmax}; buckets are {BUCKETS}")
+    dims = [int(x) for x in args.dims.split(",")]
     import numpy as np
     import torch
     from paper_1502_03391_amd import fjofc
@@ -67,42 +163,65 @@ def main(argv=None):
     from workloads import generators as gen
 
     dev = torch.device("cuda:0")
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     ctx = fjofc.Context(0)
-    rows = []
+    rows = read_cache(args.out)
     saved = os.environ.pop("FJOFC_TILE", None)
+    decided = []  # scoped FJOFC_TILE entries of this run's batch buckets
+    batch = None
     try:
-        for d in [int(x) for x in args.dims.split(",")]:
+        for d in dims:
             for nmax in buckets:
-                n = _rep_n(nmax)
-                views, _, X0 = gen.latent_views(1000 + n + d, n, args.m, 8, 0.2, d)
-                delta = [gen.pairwise_dist_torch(Y, dev) for Y in views]
-                wmat = gen.uniform_wmat(args.m, 0.5)
-                X0d = torch.from_numpy(X0.astype(np.float32)).to(dev)
-                iters = max(10, min(60, int(2e10 / (args.m * n * n))))
+                lo = _bucket_lo(nmax)
                 best = None
-                for th, var in CANDIDATES:
-                    if th > max(n, 64):
-                        continue
-                    t = _time_candidate(ctx, fjofc, delta, wmat, X0d, th, var, iters)
-                    print(f"[tune] d={d} n={n} th={th} variant={var}: {t * 1e3:.1f} us/transform",
-                          flush=True)
-                    if best is None or t < best[0]:
-                        best = (t, th, var)
-                rows.append((d, nmax, best[1], best[2], best[0], n))
-                del delta
-                torch.cuda.empty_cache()
+                use_batch = nmax <= BATCH_MAX_N
+                if use_batch:
+                    if batch is None:
+                        batch = _BatchObjective(ctx, args.batch_count, args.iters)
+                    mem = batch.members(d, lo, nmax)
+                    use_batch = bool(mem)
+                if use_batch:
+                    nbig = max(sp.n for sp in mem)
+                    for th, var in CANDIDATES:
+                        if th > max(nbig, 64):
+                            continue
+                        os.environ["FJOFC_TILE"] = ",".join(
+                            decided + [f"{d}:{lo}:{nmax}:{th}:{var}"])
+                        t = batch.cost()
+                        print(f"[tune] batch d={d} n in [{lo},{nmax}] ({len(mem)} problems) "
+                              f"th={th} variant={var}: {t * 1e3:.1f} us/transform", flush=True)
+                        if best is None or t < best[0]:
+                            best = (t, th, var)
+                    decided.append(f"{d}:{lo}:{nmax}:{best[1]}:{best[2]}")
+                    note = (f"batch of {len(batch.specs)}: {best[0] * 1e3:.1f} us/transform "
+                            f"({len(mem)} problems in the bucket)")
+                else:
+                    n = _rep_n(nmax)
+                    views, _, X0 = gen.latent_views(1000 + n + d, n, args.m, 8, 0.2, d)
+                    delta = [gen.pairwise_dist_torch(Y, dev) for Y in views]
+                    wmat = gen.uniform_wmat(args.m, 0.5)
+                    X0d = torch.from_numpy(X0.astype(np.float32)).to(dev)
+                    iters = max(10, min(60, int(2e10 / (args.m * n * n))))
+                    for th, var in CANDIDATES:
+                        if th > max(n, 64):
+                            continue
+                        os.environ["FJOFC_TILE"] = f"{th}:{var}"
+                        t = _single_cost(ctx, fjofc, delta, wmat, X0d, iters)
+                        print(f"[tune] single d={d} n={n} th={th} variant={var}: "
+                              f"{t * 1e3:.1f} us/transform", flush=True)
+                        if best is None or t < best[0]:
+                            best = (t, th, var)
+                    note = f"m={args.m} n={n}: {best[0] * 1e3:.1f} us/transform"
+                    del delta
+                    torch.cuda.empty_cache()
+                rows[(arch, d, nmax)] = (best[1], best[2], note)
     finally:
         if saved is not None:
             os.environ["FJOFC_TILE"] = saved
         else:
             os.environ.pop("FJOFC_TILE", None)
         ctx.close()
-    with open(args.out, "w") as f:
-        f.write("# fJOFC stream-kernel tuning table for gfx950 (written by autotune.py)\n")
-        f.write(f"# {time.strftime('%Y-%m-%d')} {torch.cuda.get_device_name(0)}; m={args.m}\n")
-        f.write("# d n_max tile_height variant   (measured us/transform at n)\n")
-        for d, nmax, th, var, t, n in rows:
-            f.write(f"{d} {nmax} {th} {var}   # {t * 1e3:.1f} us at n={n}\n")
+    write_cache(args.out, rows, torch.cuda.get_device_name(0))
     print(open(args.out).read(), flush=True)
 
 

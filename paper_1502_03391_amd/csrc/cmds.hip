@@ -2,11 +2,18 @@
 // first lines): classical MDS of a dissimilarity matrix A (the mean of the
 // Delta_i, or one Delta_i) needs the top eigenpairs of
 //     P = -1/2 J (A o A) J,     J = I_n - 1 1^T / n,
-// found here by subspace iteration on a block of K centred vectors V: each
-// step needs W = (A o A) V, formed by streaming A once (full rows, squared
-// on the fly); J is applied on the K columns (the host folds the column
-// means into the orthonormalisation).  Small K x K and d x d eigenproblems
-// run on the host in FP64; these kernels provide the n-long products.
+// found here by subspace iteration on a block of K centred vectors V per
+// problem: each step needs W = (A o A) V.  All m + 1 problems (the mean and
+// every Delta_i) advance together, so one step streams every Delta_i once
+// and forms all m + 1 products from the same reads (gram_kernel); J is
+// applied on the K columns (the host folds the column means into the
+// orthonormalisation).  Small K x K and d x d eigenproblems run on the host
+// in FP64; these kernels provide the n-long products.
+//
+// (A o A) V is a dense n x n by n x K contraction, so it runs on the matrix
+// cores: v_mfma_f32_16x16x4f32 with the squared entries as the A operand
+// (16 rows x 4 columns of Delta per instruction) and V as the B operand
+// (K padded to 16 columns).  FP32 products and sums, as on the vector path.
 #include "fjofc_internal.h"
 #include "wave_ops.h"
 
@@ -15,63 +22,149 @@
 namespace fjofc {
 namespace {
 
-constexpr int CM_BLOCK = 256;
-constexpr int CM_WAVES = CM_BLOCK / WAVE;
-constexpr int CM_ROWS = 4;  // rows of W per workgroup
+typedef float f4v __attribute__((ext_vector_type(4)));
 
-// W[j][c] = sum_l (scale sum_s A_s[j][l])^2 V[l][c] for the CM_ROWS rows
-// j0.. of this workgroup; the 256 threads split l (coalesced row reads).
-template <int K>
-__global__ __launch_bounds__(CM_BLOCK) void sqprod_kernel(DeltaPtrs dp, int nsrc, float scale,
-                                                          int n, const float *__restrict__ V,
-                                                          float *__restrict__ W) {
-    constexpr int VP = CM_ROWS * K;  // multiple of 16
-    __shared__ float red[CM_WAVES][VP];
-    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
-    const int j0 = blockIdx.x * CM_ROWS;
-    float acc[CM_ROWS][K];
+constexpr int GR_BLOCK = 256;
+constexpr int GR_WAVES = GR_BLOCK / WAVE;
+
+// Load 8 consecutive floats of a row from column l (l % 8 == 0); columns at
+// or beyond n read as 0.  VEC: the row is 16-byte aligned and n % 4 == 0,
+// so each half is either wholly inside or wholly outside.
+template <bool VEC>
+__device__ __forceinline__ void load8(const float *__restrict__ row, int l, int n, float (&v)[8]) {
+    if (VEC) {
 #pragma unroll
-    for (int r = 0; r < CM_ROWS; ++r)
+        for (int h = 0; h < 2; ++h) {
+            f4v q = {0.f, 0.f, 0.f, 0.f};
+            if (l + 4 * h < n) q = *reinterpret_cast<const f4v *>(row + l + 4 * h);
+            v[4 * h] = q.x;
+            v[4 * h + 1] = q.y;
+            v[4 * h + 2] = q.z;
+            v[4 * h + 3] = q.w;
+        }
+    } else {
 #pragma unroll
-        for (int c = 0; c < K; ++c) acc[r][c] = 0.f;
-    for (int l = tid; l < n; l += CM_BLOCK) {
-        float v[K];
+        for (int q = 0; q < 8; ++q) v[q] = (l + q < n) ? row[l + q] : 0.f;
+    }
+}
+
+// One wavefront: GR_ROWS rows j0.. of every problem's (A o A) V over the
+// columns [cbeg, cend) of its split, written to part.  Problems of the
+// launch: the mean (MEAN) then modalities i0 .. i0 + G - 1.  With MEAN and
+// G > 0 the launch holds all m modalities (nsrc == G) and the mean is formed
+// from the same loaded values; with G == 0 the mean sums nsrc rows itself.
+//
+// MFMA operand layout (16 x 16 x 4, wave64): lane t supplies A[t % 16][t / 16]
+// and B[t / 16][t % 16] and receives D[4 (t / 16) + r][t % 16] in register
+// r.  The contraction index k of step q stands for column l0 + 8 (t / 16) + q
+// in both operands, so each lane loads 8 consecutive columns of its row.
+template <int G, bool MEAN, bool VEC>
+__global__ __launch_bounds__(GR_BLOCK) void gram_kernel(GramArgs a) {
+    constexpr int P = G + (MEAN ? 1 : 0);
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int gw = blockIdx.x * GR_WAVES + (int)(threadIdx.x / WAVE);
+    if (gw >= a.nrowblk * a.splits) return;  // whole wavefronts; no barriers
+    const int split = gw / a.nrowblk;
+    const int rblk = gw - split * a.nrowblk;
+    const int j0 = rblk * GR_ROWS;
+    const int cbeg = split * a.cpw;
+    const int cend = min(a.n, cbeg + a.cpw);
+    const int c = lane & 15, lq = 8 * (lane >> 4);
+    f4v acc[GR_RB][P];
 #pragma unroll
-        for (int c = 0; c < K; c += 4) {
-            const float4 q = *reinterpret_cast<const float4 *>(V + (size_t)l * K + c);
-            v[c] = q.x;
-            v[c + 1] = q.y;
-            v[c + 2] = q.z;
-            v[c + 3] = q.w;
+    for (int rb = 0; rb < GR_RB; ++rb)
+#pragma unroll
+        for (int p = 0; p < P; ++p) acc[rb][p] = f4v{0.f, 0.f, 0.f, 0.f};
+    for (int l0 = cbeg; l0 < cend; l0 += GR_CHUNK) {
+        const int lb = l0 + lq;
+        // B operands: V_p[lb + q][c] from the transposed copy (zero-padded
+        // to 16 rows and npad columns)
+        float vb[P][8];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const f4v *src = reinterpret_cast<const f4v *>(a.Vt[p] + (size_t)c * a.npad + lb);
+            const f4v lo = src[0], hi = src[1];
+            vb[p][0] = lo.x; vb[p][1] = lo.y; vb[p][2] = lo.z; vb[p][3] = lo.w;
+            vb[p][4] = hi.x; vb[p][5] = hi.y; vb[p][6] = hi.z; vb[p][7] = hi.w;
         }
 #pragma unroll
-        for (int r = 0; r < CM_ROWS; ++r) {
-            const int j = j0 + r;
-            float a = 0.f;
-            if (j < n)
-                for (int s = 0; s < nsrc; ++s) a += dp.p[s][(size_t)j * n + l];
-            a *= scale;
-            const float a2 = a * a;
+        for (int rb = 0; rb < GR_RB; ++rb) {
+            const int j = j0 + rb * 16 + c;
+            float sv[P][8];
+            if (G > 0) {
+                float av[G > 0 ? G : 1][8];
 #pragma unroll
-            for (int c = 0; c < K; ++c) acc[r][c] = fmaf(a2, v[c], acc[r][c]);
+                for (int g = 0; g < G; ++g) {
+                    if (j < a.n)
+                        load8<VEC>(a.dp.p[a.i0 + g] + (size_t)j * a.n, lb, a.n, av[g]);
+                    else
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) av[g][q] = 0.f;
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    if (MEAN) {
+                        float s = 0.f;
+#pragma unroll
+                        for (int g = 0; g < G; ++g) s += av[g][q];
+                        s *= a.scale;
+                        sv[0][q] = s * s;
+                    }
+#pragma unroll
+                    for (int g = 0; g < G; ++g) sv[P - G + g][q] = av[g][q] * av[g][q];
+                }
+            } else {
+                float s[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) s[q] = 0.f;
+                if (j < a.n)
+                    for (int src = 0; src < a.nsrc; ++src) {
+                        float v[8];
+                        load8<VEC>(a.dp.p[src] + (size_t)j * a.n, lb, a.n, v);
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) s[q] += v[q];
+                    }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const float t = s[q] * a.scale;
+                    sv[0][q] = t * t;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+#pragma unroll
+                for (int p = 0; p < P; ++p)
+                    acc[rb][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(sv[p][q], vb[p][q],
+                                                                      acc[rb][p], 0, 0, 0);
         }
     }
-    float p[VP];
+    // partial results: part[split][pbase + p][row][16]
+    const int rq = 4 * (lane >> 4);
 #pragma unroll
-    for (int q = 0; q < VP; ++q) p[q] = acc[q / K][q % K];
-    float c8[VP / 8];
-    wave::reduce_scatter8<VP>(p, c8, lane);
-    if ((lane & 7) == 0) {
-        const int base = wave::scatter8_base(lane, VP);
+    for (int rb = 0; rb < GR_RB; ++rb)
 #pragma unroll
-        for (int r = 0; r < VP / 8; ++r) red[wv][base + r] = c8[r];
-    }
-    __syncthreads();
-    if (tid < VP) {
+        for (int p = 0; p < P; ++p) {
+            float *dst = a.part + (((size_t)split * a.ptotal + a.pbase + p) * a.nrow_pad +
+                                   j0 + rb * 16 + rq) * 16 + c;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) dst[r * 16] = acc[rb][p][r];
+        }
+}
+
+// W_p[j][c] = sum over splits (in order) of part[s][p][j][c], c < K.
+__global__ void gram_combine_kernel(const float *__restrict__ part, int splits, int np,
+                                    int nrow_pad, int n, int K, float *__restrict__ W,
+                                    size_t wstride) {
+    const long tot = (long)np * n * K;
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < tot;
+         q += (long)gridDim.x * blockDim.x) {
+        const int p = (int)(q / ((long)n * K));
+        const long r = q - (long)p * n * K;
+        const int j = (int)(r / K), cc = (int)(r - (long)j * K);
         float s = 0.f;
-        for (int w = 0; w < CM_WAVES; ++w) s += red[w][tid];
-        const int j = j0 + tid / K;
-        if (j < n) W[(size_t)j * K + tid % K] = s;
+        for (int sp = 0; sp < splits; ++sp)
+            s += part[(((size_t)sp * np + p) * nrow_pad + j) * 16 + cc];
+        W[p * wstride + (size_t)j * K + cc] = s;
     }
 }
 
@@ -87,72 +180,126 @@ __device__ __forceinline__ double wave_sum_d(double v) {
     return v;
 }
 
-// out[a kb + b] = sum_j A[j lda + a] B[j ldb + b] (B == nullptr: 1), FP64,
-// one workgroup per output in a fixed summation order.
-__global__ __launch_bounds__(CM_BLOCK) void cross_kernel(const float *__restrict__ A, int lda,
-                                                         const float *__restrict__ B, int ldb,
-                                                         int n, int kb, double *__restrict__ out) {
-    __shared__ double sh[CM_WAVES];
-    const int a = blockIdx.x / kb, b = blockIdx.x - a * kb;
+// For problem p = blockIdx.x / (ka kb): out_p[a kb + b] = sum_j A_p[j lda + a]
+// B_p[j ldb + b] (B == nullptr: 1), FP64, one workgroup per output in a
+// fixed summation order.
+__global__ __launch_bounds__(GR_BLOCK) void cross_kernel(const float *__restrict__ A, int lda,
+                                                         size_t sa, const float *__restrict__ B,
+                                                         int ldb, size_t sb, int n, int ka,
+                                                         int kb, double *__restrict__ out,
+                                                         size_t so) {
+    __shared__ double sh[GR_WAVES];
+    const int per = ka * kb;
+    const int p = blockIdx.x / per, o = blockIdx.x - p * per;
+    const int ai = o / kb, bi = o - ai * kb;
+    const float *Ap = A + p * sa;
+    const float *Bp = B ? B + p * sb : nullptr;
     double s = 0.0;
-    for (int j = threadIdx.x; j < n; j += CM_BLOCK)
-        s += (double)A[(size_t)j * lda + a] * (B ? (double)B[(size_t)j * ldb + b] : 1.0);
+    for (int j = threadIdx.x; j < n; j += GR_BLOCK)
+        s += (double)Ap[(size_t)j * lda + ai] * (Bp ? (double)Bp[(size_t)j * ldb + bi] : 1.0);
     s = wave_sum_d(s);
     if ((threadIdx.x & (WAVE - 1)) == 0) sh[threadIdx.x / WAVE] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
         double t = 0.0;
-        for (int w = 0; w < CM_WAVES; ++w) t += sh[w];
-        out[blockIdx.x] = t;
+        for (int w = 0; w < GR_WAVES; ++w) t += sh[w];
+        out[p * so + o] = t;
     }
 }
 
-// out[j ldo + c] = sum_a (in[j ldi + a] - mu[a]) M[a ncol + c] (FP64 sums),
-// for c < ncol; columns ncol <= c < ldo_pad of out are set to 0.
-__global__ void apply_kernel(const float *__restrict__ in, int ldi, int nin,
-                             const double *__restrict__ mu, const double *__restrict__ M,
-                             int ncol, int n, float *__restrict__ out, int ldo, int ldo_pad) {
-    const long tot = (long)n * ldo_pad;
+// For problem p = blockIdx.y: out_p[j ldo + c] = sum_a (in_p[j ldi + a] -
+// mu_p[a]) M_p[a ncol + c] (FP64 sums) for c < ncol, 0 for ncol <= c <
+// ldo_pad; optionally also the transposed copy outT_p[c][j] (rows c < 16,
+// columns j < npad, zero outside c < ncol, j < n).
+__global__ void apply_kernel(ApplyArgs a) {
+    const int p = blockIdx.y;
+    const float *in = a.in + p * a.sin;
+    const double *mu = a.mu ? a.mu + p * a.smu : nullptr;
+    const double *M = a.M + p * a.sM;
+    float *out = a.out + p * a.sout;
+    float *outT = a.outT ? a.outT + p * a.soutT : nullptr;
+    const long rows = outT ? (long)a.npad : (long)a.n;
+    const int cols = outT ? 16 : a.ldo_pad;
+    const long tot = rows * cols;
     for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < tot;
          q += (long)gridDim.x * blockDim.x) {
-        const long j = q / ldo_pad;
-        const int c = (int)(q - j * ldo_pad);
+        const long j = q / cols;
+        const int c = (int)(q - j * cols);
         double v = 0.0;
-        if (c < ncol)
-            for (int a = 0; a < nin; ++a)
-                v += ((double)in[j * ldi + a] - (mu ? mu[a] : 0.0)) * M[a * ncol + c];
-        out[j * ldo + c] = (float)v;
+        if (j < a.n && c < a.ncol)
+            for (int i = 0; i < a.nin; ++i)
+                v += ((double)in[j * a.ldi + i] - (mu ? mu[i] : 0.0)) * M[i * a.ncol + c];
+        if (j < a.n && c < a.ldo_pad) out[j * a.ldo + c] = (float)v;
+        if (outT) outT[(size_t)c * a.npad + j] = (float)v;
     }
+}
+
+template <int G, bool MEAN>
+hipError_t gram_go(const GramArgs &a, bool vec, unsigned nb, hipStream_t s) {
+    if (vec)
+        gram_kernel<G, MEAN, true><<<nb, GR_BLOCK, 0, s>>>(a);
+    else
+        gram_kernel<G, MEAN, false><<<nb, GR_BLOCK, 0, s>>>(a);
+    return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_sqprod(const DeltaPtrs &dp, int nsrc, float scale, int n, int K,
-                         const float *V, float *W, hipStream_t s) {
-    const unsigned nb = (unsigned)((n + CM_ROWS - 1) / CM_ROWS);
-    switch (K) {
-    case 4: sqprod_kernel<4><<<nb, CM_BLOCK, 0, s>>>(dp, nsrc, scale, n, V, W); break;
-    case 8: sqprod_kernel<8><<<nb, CM_BLOCK, 0, s>>>(dp, nsrc, scale, n, V, W); break;
-    case 12: sqprod_kernel<12><<<nb, CM_BLOCK, 0, s>>>(dp, nsrc, scale, n, V, W); break;
-    case 16: sqprod_kernel<16><<<nb, CM_BLOCK, 0, s>>>(dp, nsrc, scale, n, V, W); break;
+void gram_plan(int n, int &nrowblk, int &splits, int &cpw) {
+    nrowblk = (n + GR_ROWS - 1) / GR_ROWS;
+    const int chunks = (n + GR_CHUNK - 1) / GR_CHUNK;
+    // enough wavefronts to fill the chip, at least 4 column chunks each
+    int want = std::max(1, (2048 + nrowblk - 1) / nrowblk);
+    want = std::min(want, std::max(1, chunks / 4));
+    cpw = GR_CHUNK * ((chunks + want - 1) / want);
+    splits = (n + cpw - 1) / cpw;
+}
+
+hipError_t launch_gram(const GramArgs &a, int G, bool mean, hipStream_t s) {
+    const long waves = (long)a.nrowblk * a.splits;
+    const unsigned nb = (unsigned)((waves + GR_WAVES - 1) / GR_WAVES);
+    bool vec = a.n % 4 == 0;
+    for (int i = 0; i < a.nsrc && vec; ++i)
+        vec = (reinterpret_cast<uintptr_t>(a.dp.p[i]) & 15) == 0;
+    if (mean && G == 0) return gram_go<0, true>(a, vec, nb, s);
+    if (mean && G != a.nsrc) return hipErrorInvalidValue;
+    switch (G * 2 + (mean ? 1 : 0)) {
+    case 3: return gram_go<1, true>(a, vec, nb, s);
+    case 5: return gram_go<2, true>(a, vec, nb, s);
+    case 7: return gram_go<3, true>(a, vec, nb, s);
+    case 9: return gram_go<4, true>(a, vec, nb, s);
+    case 2: return gram_go<1, false>(a, vec, nb, s);
+    case 4: return gram_go<2, false>(a, vec, nb, s);
+    case 6: return gram_go<3, false>(a, vec, nb, s);
+    case 8: return gram_go<4, false>(a, vec, nb, s);
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
-hipError_t launch_cross(const float *A, int lda, int ka, const float *B, int ldb, int kb, int n,
-                        double *out, hipStream_t s) {
-    if (ka * kb == 0) return hipSuccess;
-    cross_kernel<<<(unsigned)(ka * kb), CM_BLOCK, 0, s>>>(A, lda, B, ldb, n, kb, out);
-    return hipGetLastError();
-}
-
-hipError_t launch_apply(const float *in, int ldi, int nin, const double *mu, const double *M,
-                        int ncol, int n, float *out, int ldo, int ldo_pad, hipStream_t s) {
-    const long tot = (long)n * ldo_pad;
+hipError_t launch_gram_combine(const float *part, int splits, int np, int nrow_pad, int n, int K,
+                               float *W, size_t wstride, hipStream_t s) {
+    const long tot = (long)np * n * K;
     if (tot == 0) return hipSuccess;
     const unsigned nb = (unsigned)std::min<long>(8192, (tot + 255) / 256);
-    apply_kernel<<<nb, 256, 0, s>>>(in, ldi, nin, mu, M, ncol, n, out, ldo, ldo_pad);
+    gram_combine_kernel<<<nb, 256, 0, s>>>(part, splits, np, nrow_pad, n, K, W, wstride);
+    return hipGetLastError();
+}
+
+hipError_t launch_cross(const float *A, int lda, size_t sa, int ka, const float *B, int ldb,
+                        size_t sb, int kb, int n, double *out, size_t so, int np,
+                        hipStream_t s) {
+    if (ka * kb * np == 0) return hipSuccess;
+    cross_kernel<<<(unsigned)(ka * kb * np), GR_BLOCK, 0, s>>>(A, lda, sa, B, ldb, sb, n, ka,
+                                                               kb, out, so);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply(const ApplyArgs &a, int np, hipStream_t s) {
+    const long rows = a.outT ? (long)a.npad : (long)a.n;
+    const long tot = rows * (a.outT ? 16 : a.ldo_pad);
+    if (tot == 0 || np == 0) return hipSuccess;
+    const unsigned nb = (unsigned)std::min<long>(4096, (tot + 255) / 256);
+    apply_kernel<<<dim3(nb, (unsigned)np), 256, 0, s>>>(a);
     return hipGetLastError();
 }
 

@@ -89,6 +89,7 @@ struct InstDesc {
     double *hist;       // optional: stress history (iters + 1)
     float *X;           // caller's (m n) x d configuration
     double alpha;       // relaxation: X_{t+1} = X_t + alpha (Gamma(X_t) - X_t)
+    int bnst, bnfin;    // persistent batch: tiles and finalize row items per transform
 };
 
 // One wavefront's work: tile `tile` (I << 16 | J) of modality `mod` of
@@ -133,6 +134,82 @@ hipError_t launch_copy_out(const InstDesc *insts, int count, hipStream_t s);
 hipError_t launch_to_soa(const TriGeom &g, int D, const float *X, float *Xs,
                          hipStream_t s);
 
+// ---- persistent batched launch (insample.hip) --------------------------
+// One launch runs every transform of every problem of a batch.  Workgroups
+// of BATCH_BLOCK threads take tasks from a queue in a fixed order (a task is
+// a group of tiles, of finalize row items or one reduce, of one problem); a
+// task waits (bounded) until the work it depends on, all earlier in the
+// order, has completed, as counted per problem in tiles, row items and
+// reduces:
+//   stream (t): f_done >= t bnfin   (X_t complete)
+//   reduce (t): s_done >= (t+1) bnst (every tile of transform t streamed)
+//   finalize (t): r_done >= t + 1   (transform t's reduce, hence its streams)
+// The order is transform by transform: [stream tasks][one reduce task per
+// problem][finalize tasks], the same template each transform (`tmpl`, L
+// tasks), and a last pass of streams and reduces at t = iters (the stress
+// of the returned configuration).  Every dependency of a task lies earlier
+// in the order, so with all workgroups resident the earliest unfinished
+// task can always run.
+constexpr int BATCH_BLOCK = 256;
+enum { BT_STREAM = 0, BT_RED = 1, BT_FIN = 2 };
+struct BatchTask {
+    int kind, inst;
+    int first;   // stream: first item (tile) index; finalize: first row item
+    int count;   // tiles or row items of the group (1 for a reduce)
+};
+struct BatchCtr {
+    int s_done, r_done, f_done, pad;
+};
+// What a task of `kind` at transform t waits for and which counter its
+// completion advances (by its count), for a problem with bnst tiles and
+// bnfin finalize row items per transform: counter indices 0 = s_done,
+// 1 = r_done, 2 = f_done.
+struct BatchDep {
+    int wait, need, done;
+};
+__host__ __device__ inline BatchDep batch_dep(int kind, int t, int bnst, int bnfin) {
+    if (kind == BT_STREAM) return {2, t * bnfin, 0};   // X_t complete
+    if (kind == BT_RED) return {0, (t + 1) * bnst, 1};  // transform t streamed
+    return {1, t + 1, 2};                               // transform t reduced
+}
+// Task q of the sequence: transform q / L, template position q % L.
+__host__ __device__ inline void batch_task_at(long long q, int L, int &t, int &pos) {
+    t = (int)(q / L);
+    pos = (int)(q - (long long)t * L);
+}
+struct BatchArgs {
+    const InstDesc *insts;
+    const StreamItem *items;
+    const RowItem *rows;
+    const BatchTask *tmpl;
+    int L, Lsr;           // template length; its stream + reduce prefix
+    long long ntasks;     // iters L + Lsr
+    BatchCtr *ctr;        // per problem
+    int *head;            // next task
+    int *err;             // non-zero: a wait timed out (the launch stops)
+    int *never;           // a counter no task increments (host-forced wait test)
+    int never_wait;       // 1: the first task waits on `never`
+    long long timeout;    // wall-clock ticks a wait may last
+    int iters, every, tol_mode, pad;
+    double tol;
+};
+// Zeroes head, err and the count problems' counters.
+hipError_t launch_batch_reset(const BatchArgs &a, int count, hipStream_t s);
+// maxd, maxm: the largest D and m of the batch; grid at most the resident
+// workgroups (batch_resident_blocks per CU times the CUs).
+hipError_t launch_batch_persistent(const BatchArgs &a, int maxd, int maxm, int grid, size_t lds,
+                                   hipStream_t s);
+// Workgroups of the persistent kernel one CU holds at once (0 on error).
+int batch_resident_blocks(int maxd, int maxm, size_t lds);
+// Tiles per stream task: one-wavefront tiles, four per wavefront; shared
+// tiles, four in turn.  Finalize row items per task.
+constexpr int BATCH_TILES_1W = 16, BATCH_TILES_SHARED = 4, BATCH_ROWS = 4;
+// Dynamic LDS one persistent workgroup needs for a problem's stream tasks.
+size_t batch_stream_lds(int D, int variant, size_t tile_lds);
+// Kernel variants the persistent kernel runs (one-wavefront 4 x 8 tiles,
+// 4 x 1 and 2 x 2 shared tiles).
+inline bool batch_variant_ok(int variant) { return variant == 1 || variant == 4 || variant == 5; }
+
 // ---- launchers (oos.hip) ---------------------------------------------
 struct OOSArgs {
     const float *Xs;      // in-sample configuration, SoA [m][D][npad_in]
@@ -157,17 +234,60 @@ hipError_t launch_nearest(const float *X, int m, int n, int d, const float *dnew
                           float *Y, hipStream_t s);
 
 // ---- classical MDS initialisation (cmds.hip) --------------------------
-// W (n x K) = (A o A) V with A = scale * sum of the nsrc matrices in dp
-// (n x n row-major); V, W row-major with K in {4, 8, 12, 16} columns.
-hipError_t launch_sqprod(const DeltaPtrs &dp, int nsrc, float scale, int n, int K,
-                         const float *V, float *W, hipStream_t s);
-// out (ka x kb, FP64) = A^T B over n rows (B == nullptr: column sums of A).
-hipError_t launch_cross(const float *A, int lda, int ka, const float *B, int ldb, int kb, int n,
-                        double *out, hipStream_t s);
-// out[j][c] = sum_a (in[j][a] - mu[a]) M[a][c] for c < ncol, 0 for
-// ncol <= c < ldo_pad; mu optional.
-hipError_t launch_apply(const float *in, int ldi, int nin, const double *mu, const double *M,
-                        int ncol, int n, float *out, int ldo, int ldo_pad, hipStream_t s);
+// (A o A) V for up to GR_MAXP problems of one launch: the mean of all m
+// Delta_i and/or a group of modalities.  Each wavefront takes GR_ROWS rows
+// and the cpw columns of one split; results go to part[split][p][row][16]
+// (nrow_pad = nrowblk GR_ROWS rows, 16 columns of which the first K are
+// meaningful), summed over the splits by launch_gram_combine.
+constexpr int GR_RB = 4;                // 16-row MFMA blocks per wavefront
+constexpr int GR_ROWS = 16 * GR_RB;
+constexpr int GR_CHUNK = 32;            // columns per step of a wavefront
+constexpr int GR_MAXP = 5;
+struct GramArgs {
+    DeltaPtrs dp;                 // all m matrices (n x n row-major)
+    int nsrc;                     // m: the mean's sources
+    int i0;                       // first modality of the launch's group
+    int n, npad;                  // npad: row length of Vt (multiple of 32, >= n)
+    float scale;                  // 1 / m
+    const float *Vt[GR_MAXP];     // per problem of the launch: V^T, [16][npad], zero-padded
+    float *part;
+    int pbase, ptotal;            // first global problem index; problems of the run
+    int nrowblk, splits, cpw, nrow_pad;
+};
+// Wavefront grid of an n x n product: row blocks, column splits and
+// columns per split (a multiple of GR_CHUNK).
+void gram_plan(int n, int &nrowblk, int &splits, int &cpw);
+// G modalities i0..i0+G-1 (G <= 4) and, with mean, the mean first (then
+// G == 0, or G == nsrc: the launch holds every modality).
+hipError_t launch_gram(const GramArgs &a, int G, bool mean, hipStream_t s);
+// W_p (n x K row-major, p-th at W + p wstride) = sum over splits of part.
+hipError_t launch_gram_combine(const float *part, int splits, int np, int nrow_pad, int n, int K,
+                               float *W, size_t wstride, hipStream_t s);
+// For each of np problems: out_p (ka x kb, FP64, at out + p so) = A_p^T B_p
+// over n rows (A_p = A + p sa, B_p = B + p sb; B == nullptr: column sums).
+hipError_t launch_cross(const float *A, int lda, size_t sa, int ka, const float *B, int ldb,
+                        size_t sb, int kb, int n, double *out, size_t so, int np,
+                        hipStream_t s);
+// For each problem p: out_p[j][c] = sum_a (in_p[j][a] - mu_p[a]) M_p[a][c]
+// for c < ncol, 0 for ncol <= c < ldo_pad (mu optional); with outT also
+// its transpose, [16][npad], zero outside c < ncol, j < n.
+struct ApplyArgs {
+    const float *in;
+    int ldi, nin;
+    size_t sin;
+    const double *mu;
+    size_t smu;
+    const double *M;
+    size_t sM;
+    int ncol, n;
+    float *out;
+    int ldo, ldo_pad;
+    size_t sout;
+    float *outT;
+    size_t soutT;
+    int npad;
+};
+hipError_t launch_apply(const ApplyArgs &a, int np, hipStream_t s);
 
 // ---- warm-start network (mlp.hip) -------------------------------------
 enum { GEMM_HIDDEN = 0, GEMM_LAST = 1, GEMM_BWD = 2, GEMM_STORE = 3 };
@@ -229,6 +349,19 @@ int set_error(int code, const char *fmt, ...);
 // Context services for entry points outside host.cpp: its device, its
 // device workspace (grown to at least `bytes`; contents not preserved) and
 // its pinned host staging buffer.
+// Kinds of timed work of the per-kernel profile (fjofc_profile_*).
+enum ProfKind { K_STREAM = 0, K_EDGE, K_FIN, K_RED, K_OOS, K_BATCH, K_INIT, K_KINDS };
+// Brackets what is enqueued on s during its lifetime with HIP events when
+// the context's profiling is on (host.cpp).
+struct Timed {
+    fjofc_ctx *c;
+    int kind;
+    double bytes;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    Timed(fjofc_ctx *c_, int kind_, double bytes_, hipStream_t s_);
+    ~Timed();
+};
 int ctx_device(const fjofc_ctx *ctx);
 int ctx_workspace(fjofc_ctx *ctx, size_t bytes, void **ws);
 int ctx_pinned(fjofc_ctx *ctx, size_t bytes, void **p);

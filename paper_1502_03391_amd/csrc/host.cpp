@@ -40,8 +40,6 @@ struct fjofc_ctx {
     std::vector<hipEvent_t> pool;
 };
 
-enum { K_STREAM = 0, K_EDGE, K_FIN, K_RED, K_OOS, K_BATCH, K_KINDS };
-
 namespace {
 
 thread_local std::string g_err;
@@ -125,26 +123,6 @@ hipEvent_t take_event(fjofc_ctx *c) {
     return e;
 }
 
-// Brackets one enqueued operation with events when profiling is on.
-struct Timed {
-    fjofc_ctx *c;
-    int kind;
-    double bytes;
-    hipStream_t s;
-    hipEvent_t a = nullptr;
-    Timed(fjofc_ctx *c_, int kind_, double bytes_, hipStream_t s_)
-        : c(c_), kind(kind_), bytes(bytes_), s(s_) {
-        if (c->prof && (a = take_event(c))) (void)hipEventRecord(a, s);
-    }
-    ~Timed() {
-        if (!a) return;
-        hipEvent_t b = take_event(c);
-        if (!b) return;
-        (void)hipEventRecord(b, s);
-        c->recs.push_back({kind, a, b, bytes});
-    }
-};
-
 // eq:modW: diagonal n w_ii + sum_{j != i} w_ij, off-diagonal -w_ij.
 void wmod(int m, int n, const double *w, double *W) {
     for (int i = 0; i < m; ++i) {
@@ -223,71 +201,127 @@ constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 constexpr int kDefaultVariant = 5;
 
 // Tile shape of the in-sample stream: th rows x (64 cpl) columns and the
-// kernel variant.  Order of precedence: FJOFC_TILE ("th:variant"), the
-// autotuned table (FJOFC_TUNE_TABLE, else tune_gfx950.txt next to the
-// library), the built-in default.
+// kernel variant.  Order of precedence: FJOFC_TILE, the autotuned cache
+// (FJOFC_TUNE_TABLE, else tune_cache.txt next to the library) rows of the
+// device's architecture, the built-in default.
 struct TuneRow {
+    std::string arch;
     int d, nmax, th, variant;
 };
 
 // A tile height is a multiple of the 8-row group of every variant.
 bool valid_th(int th) { return th >= 8 && th <= 2048 && th % 8 == 0; }
 
+// The cache: lines "arch d n_max tile_height variant" ('#' starts a
+// comment), read once per process.
 std::vector<TuneRow> &tune_table() {
     static std::vector<TuneRow> rows;
-    static bool loaded = false;
-    if (loaded) return rows;
-    loaded = true;
-    std::string path;
-    if (const char *e = std::getenv("FJOFC_TUNE_TABLE")) {
-        path = e;
-    } else {
-        Dl_info info;
-        if (dladdr(reinterpret_cast<void *>(&tune_table), &info) && info.dli_fname) {
-            path = info.dli_fname;
-            const size_t sl = path.rfind('/');
-            path = (sl == std::string::npos ? std::string(".") : path.substr(0, sl)) +
-                   "/tune_gfx950.txt";
+    static std::once_flag once;
+    std::call_once(once, [] {
+        std::string path;
+        if (const char *e = std::getenv("FJOFC_TUNE_TABLE")) {
+            path = e;
+        } else {
+            Dl_info info;
+            if (dladdr(reinterpret_cast<void *>(&tune_table), &info) && info.dli_fname) {
+                path = info.dli_fname;
+                const size_t sl = path.rfind('/');
+                path = (sl == std::string::npos ? std::string(".") : path.substr(0, sl)) +
+                       "/tune_cache.txt";
+            }
         }
-    }
-    if (FILE *f = path.empty() ? nullptr : std::fopen(path.c_str(), "r")) {
-        char line[256];
-        while (std::fgets(line, sizeof line, f)) {
-            TuneRow r;
-            if (line[0] == '#') continue;
-            if (std::sscanf(line, "%d %d %d %d", &r.d, &r.nmax, &r.th, &r.variant) == 4 &&
-                r.variant >= 0 && r.variant < kNumVariants && valid_th(r.th))
-                rows.push_back(r);
+        if (FILE *f = path.empty() ? nullptr : std::fopen(path.c_str(), "r")) {
+            char line[256], arch[64];
+            while (std::fgets(line, sizeof line, f)) {
+                TuneRow r;
+                if (line[0] == '#') continue;
+                if (std::sscanf(line, "%63s %d %d %d %d", arch, &r.d, &r.nmax, &r.th,
+                                &r.variant) == 5 &&
+                    r.variant >= 0 && r.variant < kNumVariants && valid_th(r.th) && r.d >= 1 &&
+                    r.nmax >= 2) {
+                    r.arch = arch;
+                    rows.push_back(r);
+                }
+            }
+            std::fclose(f);
         }
-        std::fclose(f);
-    }
+    });
     return rows;
+}
+
+// The architecture name of the current device ("gfx950" of
+// "gfx950:sramecc+:xnack-"), cached per device.
+std::string device_arch() {
+    static std::mutex mu;
+    static std::map<int, std::string> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return std::string();
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(dev);
+    if (it != cache.end()) return it->second;
+    std::string a;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        a = prop.gcnArchName;
+        a = a.substr(0, a.find(':'));
+    }
+    cache[dev] = a;
+    return a;
+}
+
+// FJOFC_TILE: "th:variant" for every problem, or a comma-separated list of
+// "d:n_lo:n_hi:th:variant" entries, each for the problems of that d with
+// n_lo <= n <= n_hi (the first matching entry applies).  Returns whether
+// it set th and variant.
+bool tile_override(int n, int d, int &th, int &variant) {
+    const char *e = std::getenv("FJOFC_TILE");
+    if (!e || !*e) return false;
+    std::string list(e);
+    size_t pos = 0;
+    while (pos <= list.size()) {
+        const size_t end = std::min(list.find(',', pos), list.size());
+        const std::string it = list.substr(pos, end - pos);
+        pos = end + 1;
+        int f[5];
+        char tail = 0;
+        const int k = std::sscanf(it.c_str(), "%d:%d:%d:%d:%d%c", &f[0], &f[1], &f[2], &f[3],
+                                  &f[4], &tail);
+        if (k == 2 && f[1] >= 0 && f[1] < kNumVariants && valid_th(f[0])) {
+            th = f[0];
+            variant = f[1];
+            return true;
+        }
+        if (k == 5 && f[0] == d && f[1] <= n && n <= f[2] && f[4] >= 0 &&
+            f[4] < kNumVariants && valid_th(f[3])) {
+            th = f[3];
+            variant = f[4];
+            return true;
+        }
+    }
+    return false;
 }
 
 void choose_tiles(int n, int d, int &th, int &variant) {
     th = 256;
     variant = kDefaultVariant;
-    // the rows of d, else those of the nearest tabulated d (the larger one
-    // on a tie): the tile follows n, and a nearby d has a similar register
-    // footprint
-    int dt = -1;
-    for (const TuneRow &r : tune_table()) {
-        const int e = std::abs(r.d - d), et = std::abs(dt - d);
-        if (dt < 0 || e < et || (e == et && r.d > dt)) dt = r.d;
-    }
-    int best = -1;
-    for (const TuneRow &r : tune_table())
-        if (r.d == dt && n <= r.nmax && (best < 0 || r.nmax < best)) {
-            best = r.nmax;
-            th = r.th;
-            variant = r.variant;
+    if (!tile_override(n, d, th, variant)) {
+        // the device's rows of d, else those of the nearest tabulated d (the
+        // larger one on a tie): the tile follows n, and a nearby d has a
+        // similar register footprint
+        const std::string arch = device_arch();
+        int dt = -1;
+        for (const TuneRow &r : tune_table()) {
+            if (r.arch != arch) continue;
+            const int e = std::abs(r.d - d), et = std::abs(dt - d);
+            if (dt < 0 || e < et || (e == et && r.d > dt)) dt = r.d;
         }
-    if (const char *e = std::getenv("FJOFC_TILE")) {
-        int a = 0, b = 0;
-        if (std::sscanf(e, "%d:%d", &a, &b) == 2 && b >= 0 && b < kNumVariants && valid_th(a)) {
-            th = a;
-            variant = b;
-        }
+        int best = -1;
+        for (const TuneRow &r : tune_table())
+            if (r.arch == arch && r.d == dt && n <= r.nmax && (best < 0 || r.nmax < best)) {
+                best = r.nmax;
+                th = r.th;
+                variant = r.variant;
+            }
     }
     // each of the variant's R row slabs holds whole 8-row groups
     const int unit = 8 * kVariants[variant].r;
@@ -728,6 +762,19 @@ int run_insample(fjofc_ctx *ctx, const float *const *delta, int m, int n,
 
 }  // namespace
 
+fjofc::Timed::Timed(fjofc_ctx *c_, int kind_, double bytes_, hipStream_t s_)
+    : c(c_), kind(kind_), bytes(bytes_), s(s_) {
+    if (c->prof && (a = take_event(c))) (void)hipEventRecord(a, s);
+}
+
+fjofc::Timed::~Timed() {
+    if (!a) return;
+    hipEvent_t b = take_event(c);
+    if (!b) return;
+    (void)hipEventRecord(b, s);
+    c->recs.push_back({kind, a, b, bytes});
+}
+
 int fjofc::ctx_device(const fjofc_ctx *ctx) { return ctx->device; }
 
 int fjofc::ctx_workspace(fjofc_ctx *ctx, size_t bytes, void **ws) {
@@ -776,6 +823,14 @@ struct fjofc_batch {
     double key_tol = -1.0;
     EmbedState *pinned = nullptr;
     EmbedState *d_st = nullptr;
+    // persistent launch: planned when every problem's tile variant is one the
+    // persistent kernel runs (persist_ok); chosen with fjofc_batch_set_launch
+    // (persist).  The default is the lockstep graph of per-group launches.
+    bool persist_ok = false, persist = false;
+    int maxd = 0, pgrid = 0;
+    size_t plds = 0;
+    BatchArgs pargs{};
+    int *pin_err = nullptr;  // pinned copy of the error flag
 };
 
 namespace {
@@ -791,6 +846,7 @@ void batch_free(fjofc_batch *b) {
     if (b->fork.fork) (void)hipEventDestroy(b->fork.fork);
     if (b->mem) (void)hipFree(b->mem);
     if (b->pinned) (void)hipHostFree(b->pinned);
+    if (b->pin_err) (void)hipHostFree(b->pin_err);
     delete b;
 }
 
@@ -967,6 +1023,41 @@ int oos_run(fjofc_ctx *ctx, const float *X_in, int m, int n, int d, const double
 
 }  // namespace
 
+namespace {
+
+// The persistent batch as one captured sequence: X0 to SoA and the loop
+// state (init), the commensurability of X0, the queue reset, the persistent
+// launch, and the copy of the results back to the callers' layout.
+int enqueue_persistent(fjofc_batch *b, int iters, double tol, int tol_mode, int stress_every) {
+    hipStream_t s = b->cs;
+    BatchArgs a = b->pargs;
+    a.ntasks = (long long)iters * a.L + a.Lsr;
+    a.iters = iters;
+    a.every = stress_every;
+    a.tol = tol;
+    a.tol_mode = tol_mode;
+    // wall-clock ticks a dependency wait may last (FJOFC_BATCH_TIMEOUT_MS,
+    // default 5000 ms); FJOFC_BATCH_FORCE_WAIT makes the first task wait on
+    // a counter no task increments (a test of the timeout path)
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, b->ctx->device) != hipSuccess ||
+        khz <= 0)
+        khz = 100000;
+    double ms = 5000.0;
+    if (const char *e = std::getenv("FJOFC_BATCH_TIMEOUT_MS")) ms = std::max(0.0, std::atof(e));
+    a.timeout = (long long)(ms * khz);
+    const char *fw = std::getenv("FJOFC_BATCH_FORCE_WAIT");
+    a.never_wait = (fw && fw[0] && fw[0] != '0') ? 1 : 0;
+    HIP_TRY(launch_init(b->d_insts, b->count, 0, s));
+    HIP_TRY(launch_com(b->d_insts, b->d_rows, b->nrows, s));
+    HIP_TRY(launch_batch_reset(a, b->count, s));
+    HIP_TRY(launch_batch_persistent(a, b->maxd, b->maxm, b->pgrid, b->plds, s));
+    HIP_TRY(launch_copy_out(b->d_insts, b->count, s));
+    return FJOFC_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *fjofc_last_error(void) { return g_err.c_str(); }
@@ -1138,6 +1229,9 @@ int fjofc_profile_read(fjofc_ctx *ctx, fjofc_profile *out) {
     out->batch_launches = cnt[K_BATCH];
     out->batch_ms = ms[K_BATCH];
     out->batch_bytes = by[K_BATCH];
+    out->init_launches = cnt[K_INIT];
+    out->init_ms = ms[K_INIT];
+    out->init_bytes = by[K_INIT];
     return FJOFC_OK;
 }
 
@@ -1195,9 +1289,63 @@ int fjofc_batch_create(fjofc_ctx *ctx, const fjofc_problem *probs, int count,
         r[1] = (int)rows.size() - r[0];
         grows[kv.first] = r;
     }
+    // Persistent plan: per problem (largest first) its stream tasks (four
+    // one-wavefront tiles or one shared tile each) and finalize row items;
+    // the template is [all stream tasks][one reduce per problem][all
+    // finalize tasks].
+    b->persist_ok = true;
+    for (int p = 0; p < count; ++p) {
+        if (!batch_variant_ok(b->hi[p].g.variant)) b->persist_ok = false;
+        b->maxd = std::max(b->maxd, b->hi[p].D);
+    }
+    std::vector<StreamItem> pitems;
+    std::vector<RowItem> prows;
+    std::vector<BatchTask> tstream, tred, tfin;
+    std::vector<int> nst(count, 0), nfin(count, 0);
+    if (b->persist_ok) {
+        for (int p : order) {
+            const HostInst &h = b->hi[p];
+            std::vector<StreamItem> its;
+            append_items(p, h, its);
+            const int per = h.g.variant == 1 ? BATCH_TILES_1W : BATCH_TILES_SHARED;
+            for (size_t q = 0; q < its.size(); q += per) {
+                const int cnt = (int)std::min<size_t>(per, its.size() - q);
+                tstream.push_back({BT_STREAM, p, (int)(pitems.size() + q), cnt});
+            }
+            nst[p] = (int)its.size();
+            pitems.insert(pitems.end(), its.begin(), its.end());
+            tred.push_back({BT_RED, p, 0, 1});
+            std::vector<RowItem> rs;
+            append_rows(p, h, rs);
+            for (size_t q = 0; q < rs.size(); q += BATCH_ROWS) {
+                const int cnt = (int)std::min<size_t>(BATCH_ROWS, rs.size() - q);
+                tfin.push_back({BT_FIN, p, (int)(prows.size() + q), cnt});
+            }
+            nfin[p] = (int)rs.size();
+            prows.insert(prows.end(), rs.begin(), rs.end());
+            b->plds = std::max(b->plds, batch_stream_lds(h.D, h.g.variant, stream_lds(h.g, h.D)));
+        }
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device) !=
+            hipSuccess)
+            ncu = 0;
+        const int per_cu = batch_resident_blocks(b->maxd, b->maxm, b->plds);
+        b->pgrid = per_cu * ncu;
+        if (b->pgrid < 1) b->persist_ok = false;
+    }
+    std::vector<BatchTask> tmpl;
+    tmpl.insert(tmpl.end(), tstream.begin(), tstream.end());
+    tmpl.insert(tmpl.end(), tred.begin(), tred.end());
+    tmpl.insert(tmpl.end(), tfin.begin(), tfin.end());
+
     Carve cv;
     const size_t o_insts = cv.take<InstDesc>(count);
     const size_t o_st = cv.take<EmbedState>(count);
+    const size_t o_tmpl = cv.take<BatchTask>(std::max<size_t>(1, tmpl.size()));
+    const size_t o_pitems = cv.take<StreamItem>(std::max<size_t>(1, pitems.size()));
+    const size_t o_prows = cv.take<RowItem>(std::max<size_t>(1, prows.size()));
+    const size_t o_ctr = cv.take<BatchCtr>(count);
+    const size_t o_flags = cv.take<long long>(4);  // head, err, never
     std::vector<size_t> o_groups;
     for (auto &kv : gitems) o_groups.push_back(cv.take<StreamItem>(kv.second.size()));
     const size_t o_rows = cv.take<RowItem>(rows.size());
@@ -1221,6 +1369,8 @@ int fjofc_batch_create(fjofc_ctx *ctx, const fjofc_problem *probs, int count,
     };
     for (int p = 0; p < count; ++p) {
         descs[p] = make_desc(base, b->hi[p], offs[p].data(), d_st + p);
+        descs[p].bnst = nst[p];
+        descs[p].bnfin = nfin[p];
         copy(const_cast<double *>(descs[p].Winv), b->hi[p].Winv.data(),
              sizeof(double) * b->hi[p].Winv.size());
         copy(const_cast<double *>(descs[p].wmat), b->hi[p].wmat.data(),
@@ -1239,6 +1389,28 @@ int fjofc_batch_create(fjofc_ctx *ctx, const fjofc_problem *probs, int count,
     }
     b->nrows = (int)rows.size();
     copy(b->d_rows, rows.data(), rows.size() * sizeof(RowItem));
+    if (b->persist_ok) {
+        BatchArgs &a = b->pargs;
+        a.insts = b->d_insts;
+        a.items = reinterpret_cast<const StreamItem *>(base + o_pitems);
+        a.rows = reinterpret_cast<const RowItem *>(base + o_prows);
+        a.tmpl = reinterpret_cast<const BatchTask *>(base + o_tmpl);
+        a.L = (int)tmpl.size();
+        a.Lsr = (int)(tstream.size() + tred.size());
+        a.ctr = reinterpret_cast<BatchCtr *>(base + o_ctr);
+        long long *flags = reinterpret_cast<long long *>(base + o_flags);
+        a.head = reinterpret_cast<int *>(flags);
+        a.err = reinterpret_cast<int *>(flags + 1);
+        a.never = reinterpret_cast<int *>(flags + 2);
+        copy(base + o_tmpl, tmpl.data(), tmpl.size() * sizeof(BatchTask));
+        copy(base + o_pitems, pitems.data(), pitems.size() * sizeof(StreamItem));
+        copy(base + o_prows, prows.data(), prows.size() * sizeof(RowItem));
+        if (!rc && hipHostMalloc(reinterpret_cast<void **>(&b->pin_err), 256,
+                                 hipHostMallocDefault) != hipSuccess) {
+            b->pin_err = nullptr;
+            rc = fail(FJOFC_ENOMEM, "pinned batch flag");
+        }
+    }
     if (!rc && (hipStreamCreate(&b->cs) != hipSuccess ||
                 hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
                 hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess))
@@ -1292,8 +1464,11 @@ int fjofc_batch_run(fjofc_batch *b, int iters, double tol, int tol_mode, int str
         const bool prof = ctx->prof;
         ctx->prof = false;  // no event records inside the captured graph
         HIP_TRY(hipStreamBeginCapture(b->cs, hipStreamCaptureModeThreadLocal));
-        rc = enqueue_loop(ctx, b->d_insts, b->count, b->maxm, b->groups, b->d_rows, b->nrows,
-                          iters, tol, tol_mode, stress_every, 0, false, b->cs, &b->fork);
+        if (b->persist)
+            rc = enqueue_persistent(b, iters, tol, tol_mode, stress_every);
+        else
+            rc = enqueue_loop(ctx, b->d_insts, b->count, b->maxm, b->groups, b->d_rows, b->nrows,
+                              iters, tol, tol_mode, stress_every, 0, false, b->cs, &b->fork);
         const hipError_t ec = hipStreamEndCapture(b->cs, &b->graph);
         ctx->prof = prof;
         if (rc) return rc;
@@ -1314,6 +1489,17 @@ int fjofc_batch_run(fjofc_batch *b, int iters, double tol, int tol_mode, int str
     }
     HIP_TRY(hipEventRecord(b->ev_out, b->cs));
     HIP_TRY(hipStreamWaitEvent(s, b->ev_out, 0));
+    if (b->persist) {
+        // a dependency wait that timed out (workgroups not all resident, or
+        // the host-forced wait test) ends the launch early: report it
+        HIP_TRY(hipMemcpyAsync(b->pin_err, b->pargs.err, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (*b->pin_err)
+            return fail(FJOFC_EHIP,
+                        "persistent batch: a dependency wait timed out (all %d workgroups must "
+                        "be resident at once); the results are incomplete",
+                        b->pgrid);
+    }
     if (res) {
         HIP_TRY(hipMemcpyAsync(b->pinned, b->d_st, sizeof(EmbedState) * b->count,
                                hipMemcpyDeviceToHost, s));
@@ -1334,6 +1520,36 @@ int fjofc_embed_batched(fjofc_ctx *ctx, const fjofc_problem *probs, int count, i
     if (!res) (void)hipStreamSynchronize(static_cast<hipStream_t>(stream));
     fjofc_batch_destroy(b);
     return rc;
+}
+
+int fjofc_tile_choice(fjofc_ctx *ctx, int n, int d, int *tile_height, int *variant) {
+    if (!ctx || !tile_height || !variant) return fail(FJOFC_EINVAL, "NULL argument");
+    if (n < 2 || d < 1 || d > FJOFC_MAX_D) return fail(FJOFC_EINVAL, "n=%d, d=%d", n, d);
+    DeviceGuard dg(ctx->device);
+    choose_tiles(n, d, *tile_height, *variant);
+    return FJOFC_OK;
+}
+
+int fjofc_batch_set_launch(fjofc_batch *b, int launch) {
+    if (!b) return fail(FJOFC_EINVAL, "batch is NULL");
+    if (launch != FJOFC_LAUNCH_LOCKSTEP && launch != FJOFC_LAUNCH_PERSISTENT)
+        return fail(FJOFC_EINVAL, "unknown batch launch %d", launch);
+    const bool want = launch == FJOFC_LAUNCH_PERSISTENT;
+    if (want && !b->persist_ok)
+        return fail(FJOFC_EINVAL,
+                    "the persistent launch does not run this batch (a tile shape it has no "
+                    "variant for, or no workgroup fits a CU)");
+    if (want != b->persist) {
+        // the captured graph belongs to the other launch: capture again
+        DeviceGuard dg(b->ctx->device);
+        (void)hipStreamSynchronize(b->cs);
+        if (b->exec) (void)hipGraphExecDestroy(b->exec);
+        if (b->graph) (void)hipGraphDestroy(b->graph);
+        b->exec = nullptr;
+        b->graph = nullptr;
+        b->persist = want;
+    }
+    return FJOFC_OK;
 }
 
 void fjofc_batch_destroy(fjofc_batch *b) {

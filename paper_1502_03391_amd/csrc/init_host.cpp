@@ -5,13 +5,16 @@
 //   X^(i)_0 = orthogonal Procrustes fit of xi_i onto xi_0.
 // cMDS of A: the d largest eigenpairs (lambda_k, u_k) of
 // P = -1/2 J (A o A) J, X = [u_1 .. u_d] diag(lambda)^(1/2).  They come from
-// subspace iteration on K >= d centred vectors: W = (A o A) V on the GPU
-// (one full stream of A), then on the host (FP64, K x K) the centred Gram
-// W^T J W is diagonalised and V <- J W S diag(g)^(-1/2) is formed on the
-// GPU; after the last step the Rayleigh-Ritz matrix V^T P V gives the Ritz
-// pairs.  Procrustes: with M = xi_i^T xi_0, the rotation maximising
-// tr(Q^T M) is the polar factor Q = M (M^T M)^(-1/2) (the printed
-// xi_i U V^T with U S V^T = xi_0^T xi_i is its transpose; the fit uses Q).
+// subspace iteration on K >= d centred vectors: W = (A o A) V on the GPU,
+// then on the host (FP64, K x K) the centred Gram W^T J W is diagonalised
+// and V <- J W S diag(g)^(-1/2) is formed on the GPU; after the last step
+// the Rayleigh-Ritz matrix V^T P V gives the Ritz pairs.  The m + 1
+// problems (the mean and every Delta_i) take their steps together: one
+// pass over the Delta_i per step forms all m + 1 products, and one host
+// round trip per step serves every problem.  Procrustes: with
+// M = xi_i^T xi_0, the rotation maximising tr(Q^T M) is the polar factor
+// Q = M (M^T M)^(-1/2) (the printed xi_i U V^T with U S V^T = xi_0^T xi_i is
+// its transpose; the fit uses Q).
 #include "fjofc.h"
 #include "fjofc_internal.h"
 
@@ -95,79 +98,173 @@ uint64_t splitmix(uint64_t x) {
 }
 
 struct InitBufs {
-    float *V, *W, *xi0, *xi;
-    double *stats, *small;  // K*K + K doubles each
-    double *pin;            // pinned host copy of stats / small
+    int P, K, n, d, npad;
+    float *V, *W, *Vt, *part, *xi;  // per problem: n K, n K, 16 npad, -, n d
+    double *stats, *small;          // per problem K K + K doubles each
+    double *pin;                    // pinned host copy of stats / small
+    int nrowblk, splits, cpw;
+    size_t nK() const { return (size_t)n * K; }
+    size_t kk() const { return (size_t)K * K + K; }
 };
 
 // Host step of one orthonormalisation: from the Gram G = W^T W and the
 // column sums cs of W (n rows), the matrix M with V = (W - 1 cs^T / n) M
 // orthonormal (columns of negligible weight become 0).
-void ortho_matrix(int K, int n, const double *G, const double *cs, std::vector<double> &M,
-                  std::vector<double> &mu) {
+void ortho_matrix(int K, int n, const double *G, const double *cs, double *M, double *mu) {
     std::vector<double> Gc((size_t)K * K);
     for (int a = 0; a < K; ++a)
         for (int b = 0; b < K; ++b) Gc[(size_t)a * K + b] = G[a * K + b] - cs[a] * cs[b] / n;
     std::vector<double> w, S;
     jacobi_eigh(K, Gc, w, S);
-    M.assign((size_t)K * K, 0.0);
+    std::fill(M, M + (size_t)K * K, 0.0);
     const double top = std::max(w[0], 0.0);
     for (int c = 0; c < K; ++c) {
         if (!(w[c] > 1e-12 * top) || w[c] <= 0.0) continue;
         const double s = 1.0 / std::sqrt(w[c]);
         for (int a = 0; a < K; ++a) M[(size_t)a * K + c] = S[(size_t)a * K + c] * s;
     }
-    mu.resize(K);
     for (int a = 0; a < K; ++a) mu[a] = cs[a] / n;
 }
 
-// cMDS of A = scale * sum of the nsrc matrices: xi (n x d, device) and the
-// d largest Ritz values.
-int cmds(const DeltaPtrs &dp, int nsrc, float scale, int n, int d, int K, int iters,
-         uint64_t seed, const InitBufs &b, float *xi, double *eig, hipStream_t s) {
-    const size_t KK = (size_t)K * K;
-    // seeded start in [-1, 1)
+// W_p = (A_p o A_p) V_p for every problem: problem 0 the mean of the m
+// matrices, problem 1 + i Delta_i.  m <= 4: one pass over the matrices;
+// otherwise a pass for the mean and one per group of four modalities.
+int products(fjofc_ctx *ctx, const DeltaPtrs &dp, int m, const InitBufs &b, hipStream_t s) {
+    // every entry of every Delta_i once, and once more for the mean when
+    // it takes a pass of its own
+    const double rd = 4.0 * (double)b.n * b.n * (m <= 4 ? m : 2 * m);
+    Timed tm(ctx, K_INIT, rd, s);
+    GramArgs ga{};
+    ga.dp = dp;
+    ga.nsrc = m;
+    ga.n = b.n;
+    ga.npad = b.npad;
+    ga.scale = (float)(1.0 / m);
+    ga.part = b.part;
+    ga.ptotal = b.P;
+    ga.nrowblk = b.nrowblk;
+    ga.splits = b.splits;
+    ga.cpw = b.cpw;
+    ga.nrow_pad = b.nrowblk * GR_ROWS;
+    const size_t vts = (size_t)16 * b.npad;
+    if (m <= 4) {
+        for (int p = 0; p <= m; ++p) ga.Vt[p] = b.Vt + p * vts;
+        INIT_TRY(launch_gram(ga, m, true, s));
+    } else {
+        ga.Vt[0] = b.Vt;
+        INIT_TRY(launch_gram(ga, 0, true, s));
+        for (int g0 = 0; g0 < m; g0 += 4) {
+            const int G = std::min(4, m - g0);
+            ga.i0 = g0;
+            ga.pbase = 1 + g0;
+            for (int q = 0; q < G; ++q) ga.Vt[q] = b.Vt + (1 + g0 + q) * vts;
+            INIT_TRY(launch_gram(ga, G, false, s));
+        }
+    }
+    INIT_TRY(launch_gram_combine(b.part, b.splits, b.P, ga.nrow_pad, b.n, b.K, b.W, b.nK(), s));
+    return FJOFC_OK;
+}
+
+// V_p (and its transpose) = (in_p - 1 mu_p^T) M_p with M_p, mu_p from b.small.
+int apply_all(const InitBufs &b, const float *in, hipStream_t s) {
+    ApplyArgs aa{};
+    aa.in = in;
+    aa.ldi = b.K;
+    aa.nin = b.K;
+    aa.sin = b.nK();
+    aa.mu = b.small + (size_t)b.K * b.K;
+    aa.smu = b.kk();
+    aa.M = b.small;
+    aa.sM = b.kk();
+    aa.ncol = b.K;
+    aa.n = b.n;
+    aa.out = b.V;
+    aa.ldo = b.K;
+    aa.ldo_pad = b.K;
+    aa.sout = b.nK();
+    aa.outT = b.Vt;
+    aa.soutT = (size_t)16 * b.npad;
+    aa.npad = b.npad;
+    INIT_TRY(launch_apply(aa, b.P, s));
+    return FJOFC_OK;
+}
+
+// cMDS of all P problems: xi_p (n x d, device, at b.xi + p n d) and the d
+// largest Ritz values of each (eig + p d).
+int cmds_all(fjofc_ctx *ctx, const DeltaPtrs &dp, int m, int iters, const InitBufs &b,
+             double *eig, hipStream_t s) {
+    const int K = b.K, P = b.P, d = b.d;
+    const size_t KK = (size_t)K * K, kk = b.kk();
+    // seeded starts in [-1, 1): the mean's stream 1, Delta_i's stream 2 + i
     {
-        std::vector<float> R((size_t)n * K);
-        for (size_t q = 0; q < R.size(); ++q)
-            R[q] = (float)((double)(splitmix(seed * 0x100000001B3ull + q) >> 11) * 0x1.0p-52 - 1.0);
+        std::vector<float> R((size_t)P * b.nK());
+        for (int p = 0; p < P; ++p) {
+            const uint64_t seed = 1 + (uint64_t)p;
+            float *r = R.data() + p * b.nK();
+            for (size_t q = 0; q < b.nK(); ++q)
+                r[q] = (float)((double)(splitmix(seed * 0x100000001B3ull + q) >> 11) * 0x1.0p-52 -
+                               1.0);
+        }
         INIT_TRY(hipMemcpyAsync(b.W, R.data(), sizeof(float) * R.size(), hipMemcpyHostToDevice, s));
         INIT_TRY(hipStreamSynchronize(s));
     }
-    std::vector<double> M, mu;
     for (int it = 0; it <= iters; ++it) {
-        if (it > 0) INIT_TRY(launch_sqprod(dp, nsrc, scale, n, K, b.V, b.W, s));
-        INIT_TRY(launch_cross(b.W, K, K, b.W, K, K, n, b.stats, s));
-        INIT_TRY(launch_cross(b.W, K, K, nullptr, 0, 1, n, b.stats + KK, s));
-        INIT_TRY(hipMemcpyAsync(b.pin, b.stats, sizeof(double) * (KK + K), hipMemcpyDeviceToHost, s));
+        if (it > 0) {
+            const int rc = products(ctx, dp, m, b, s);
+            if (rc) return rc;
+        }
+        INIT_TRY(launch_cross(b.W, K, b.nK(), K, b.W, K, b.nK(), K, b.n, b.stats, kk, P, s));
+        INIT_TRY(launch_cross(b.W, K, b.nK(), K, nullptr, 0, 0, 1, b.n, b.stats + KK, kk, P, s));
+        INIT_TRY(hipMemcpyAsync(b.pin, b.stats, sizeof(double) * kk * P, hipMemcpyDeviceToHost, s));
         INIT_TRY(hipStreamSynchronize(s));
-        ortho_matrix(K, n, b.pin, b.pin + KK, M, mu);
-        std::memcpy(b.pin, M.data(), sizeof(double) * KK);
-        std::memcpy(b.pin + KK, mu.data(), sizeof(double) * K);
-        INIT_TRY(hipMemcpyAsync(b.small, b.pin, sizeof(double) * (KK + K), hipMemcpyHostToDevice, s));
-        INIT_TRY(launch_apply(b.W, K, K, b.small + KK, b.small, K, n, b.V, K, K, s));
+        std::vector<double> out(kk * P);
+        for (int p = 0; p < P; ++p)
+            ortho_matrix(K, b.n, b.pin + p * kk, b.pin + p * kk + KK, out.data() + p * kk,
+                         out.data() + p * kk + KK);
+        std::memcpy(b.pin, out.data(), sizeof(double) * kk * P);
+        INIT_TRY(hipMemcpyAsync(b.small, b.pin, sizeof(double) * kk * P, hipMemcpyHostToDevice, s));
+        const int rc = apply_all(b, b.W, s);
+        if (rc) return rc;
         INIT_TRY(hipStreamSynchronize(s));  // b.pin is reused next
     }
     // Rayleigh-Ritz: V^T P V = -1/2 V^T (A o A) V (V is centred)
-    INIT_TRY(launch_sqprod(dp, nsrc, scale, n, K, b.V, b.W, s));
-    INIT_TRY(launch_cross(b.V, K, K, b.W, K, K, n, b.stats, s));
-    INIT_TRY(hipMemcpyAsync(b.pin, b.stats, sizeof(double) * KK, hipMemcpyDeviceToHost, s));
+    int rc = products(ctx, dp, m, b, s);
+    if (rc) return rc;
+    INIT_TRY(launch_cross(b.V, K, b.nK(), K, b.W, K, b.nK(), K, b.n, b.stats, kk, P, s));
+    INIT_TRY(hipMemcpyAsync(b.pin, b.stats, sizeof(double) * kk * P, hipMemcpyDeviceToHost, s));
     INIT_TRY(hipStreamSynchronize(s));
-    std::vector<double> H(KK);
-    for (int a = 0; a < K; ++a)
-        for (int c = 0; c < K; ++c)
-            H[(size_t)a * K + c] = -0.25 * (b.pin[a * K + c] + b.pin[c * K + a]);
-    std::vector<double> th, S;
-    jacobi_eigh(K, H, th, S);
-    std::vector<double> M2((size_t)K * d, 0.0);
-    for (int c = 0; c < d; ++c) {
-        const double sc = std::sqrt(std::max(th[c], 0.0));
-        for (int a = 0; a < K; ++a) M2[(size_t)a * d + c] = S[(size_t)a * K + c] * sc;
-        if (eig) eig[c] = th[c];
+    std::vector<double> M2(kk * P, 0.0);
+    for (int p = 0; p < P; ++p) {
+        const double *g = b.pin + p * kk;
+        std::vector<double> H(KK);
+        for (int a = 0; a < K; ++a)
+            for (int c = 0; c < K; ++c)
+                H[(size_t)a * K + c] = -0.25 * (g[a * K + c] + g[c * K + a]);
+        std::vector<double> th, S;
+        jacobi_eigh(K, H, th, S);
+        double *Mp = M2.data() + p * kk;  // K x d
+        for (int c = 0; c < d; ++c) {
+            const double sc = std::sqrt(std::max(th[c], 0.0));
+            for (int a = 0; a < K; ++a) Mp[(size_t)a * d + c] = S[(size_t)a * K + c] * sc;
+            if (eig) eig[(size_t)p * d + c] = th[c];
+        }
     }
-    std::memcpy(b.pin, M2.data(), sizeof(double) * K * d);
-    INIT_TRY(hipMemcpyAsync(b.small, b.pin, sizeof(double) * K * d, hipMemcpyHostToDevice, s));
-    INIT_TRY(launch_apply(b.V, K, K, nullptr, b.small, d, n, xi, d, d, s));
+    std::memcpy(b.pin, M2.data(), sizeof(double) * kk * P);
+    INIT_TRY(hipMemcpyAsync(b.small, b.pin, sizeof(double) * kk * P, hipMemcpyHostToDevice, s));
+    ApplyArgs aa{};
+    aa.in = b.V;
+    aa.ldi = K;
+    aa.nin = K;
+    aa.sin = b.nK();
+    aa.M = b.small;
+    aa.sM = kk;
+    aa.ncol = d;
+    aa.n = b.n;
+    aa.out = b.xi;
+    aa.ldo = d;
+    aa.ldo_pad = d;
+    aa.sout = (size_t)b.n * d;
+    INIT_TRY(launch_apply(aa, P, s));
     INIT_TRY(hipStreamSynchronize(s));
     return FJOFC_OK;
 }
@@ -199,24 +296,33 @@ extern "C" int fjofc_init_cmds(fjofc_ctx *ctx, const float *const *delta, int m,
     hipStream_t s = static_cast<hipStream_t>(stream);
 
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-    const size_t KK = (size_t)K * K;
+    InitBufs b;
+    b.P = m + 1;
+    b.K = K;
+    b.n = n;
+    b.d = d;
+    b.npad = (n + GR_CHUNK - 1) / GR_CHUNK * GR_CHUNK;
+    gram_plan(n, b.nrowblk, b.splits, b.cpw);
+    const size_t kk = b.kk(), P = (size_t)b.P;
     size_t off = 0;
-    const size_t oV = off; off = al(off + sizeof(float) * n * K);
-    const size_t oW = off; off = al(off + sizeof(float) * n * K);
-    const size_t oX0 = off; off = al(off + sizeof(float) * n * d);
-    const size_t oXi = off; off = al(off + sizeof(float) * n * d);
-    const size_t oSt = off; off = al(off + sizeof(double) * (KK + K));
-    const size_t oSm = off; off = al(off + sizeof(double) * (KK + K));
+    const size_t oV = off; off = al(off + sizeof(float) * P * b.nK());
+    const size_t oW = off; off = al(off + sizeof(float) * P * b.nK());
+    const size_t oVt = off; off = al(off + sizeof(float) * P * 16 * b.npad);
+    const size_t oPt = off;
+    off = al(off + sizeof(float) * (size_t)b.splits * P * b.nrowblk * GR_ROWS * 16);
+    const size_t oXi = off; off = al(off + sizeof(float) * P * n * d);
+    const size_t oSt = off; off = al(off + sizeof(double) * P * kk);
+    const size_t oSm = off; off = al(off + sizeof(double) * P * kk);
     void *ws = nullptr, *pin = nullptr;
     int rc = ctx_workspace(ctx, off, &ws);
     if (rc) return rc;
-    rc = ctx_pinned(ctx, sizeof(double) * (KK + K), &pin);
+    rc = ctx_pinned(ctx, sizeof(double) * P * kk, &pin);
     if (rc) return rc;
     char *base = static_cast<char *>(ws);
-    InitBufs b;
     b.V = reinterpret_cast<float *>(base + oV);
     b.W = reinterpret_cast<float *>(base + oW);
-    b.xi0 = reinterpret_cast<float *>(base + oX0);
+    b.Vt = reinterpret_cast<float *>(base + oVt);
+    b.part = reinterpret_cast<float *>(base + oPt);
     b.xi = reinterpret_cast<float *>(base + oXi);
     b.stats = reinterpret_cast<double *>(base + oSt);
     b.small = reinterpret_cast<double *>(base + oSm);
@@ -225,25 +331,24 @@ extern "C" int fjofc_init_cmds(fjofc_ctx *ctx, const float *const *delta, int m,
 
     DeltaPtrs all{};
     for (int i = 0; i < m; ++i) all.p[i] = delta[i];
-    rc = cmds(all, m, (float)(1.0 / m), n, d, K, iters, 1, b, b.xi0, eigvals, s);
+    rc = cmds_all(ctx, all, m, iters, b, eigvals, s);
     if (rc) return rc;
+    // Procrustes of every xi_i (problem 1 + i) onto xi_0:
+    // M_i = xi_i^T xi_0, Q_i = M_i (M_i^T M_i)^(-1/2)
+    const size_t dd = (size_t)d * d, nd = (size_t)n * d;
+    INIT_TRY(launch_cross(b.xi + nd, d, nd, d, b.xi, d, 0, d, n, b.stats, dd, m, s));
+    INIT_TRY(hipMemcpyAsync(b.pin, b.stats, sizeof(double) * dd * m, hipMemcpyDeviceToHost, s));
+    INIT_TRY(hipStreamSynchronize(s));
+    std::vector<double> Qall(dd * m);
     for (int i = 0; i < m; ++i) {
-        DeltaPtrs one{};
-        one.p[0] = delta[i];
-        rc = cmds(one, 1, 1.0f, n, d, K, iters, 2 + (uint64_t)i, b, b.xi,
-                  eigvals ? eigvals + (size_t)(i + 1) * d : nullptr, s);
-        if (rc) return rc;
-        // Procrustes: M = xi_i^T xi_0, Q = M (M^T M)^(-1/2)
-        INIT_TRY(launch_cross(b.xi, d, d, b.xi0, d, d, n, b.stats, s));
-        INIT_TRY(hipMemcpyAsync(b.pin, b.stats, sizeof(double) * d * d, hipMemcpyDeviceToHost, s));
-        INIT_TRY(hipStreamSynchronize(s));
-        std::vector<double> Mq(b.pin, b.pin + (size_t)d * d), MtM((size_t)d * d, 0.0);
+        const double *Mq = b.pin + i * dd;
+        std::vector<double> MtM(dd, 0.0);
         for (int a = 0; a < d; ++a)
             for (int c = 0; c < d; ++c)
                 for (int r = 0; r < d; ++r) MtM[(size_t)a * d + c] += Mq[(size_t)r * d + a] * Mq[(size_t)r * d + c];
         std::vector<double> w, S;
         jacobi_eigh(d, MtM, w, S);
-        std::vector<double> Ris((size_t)d * d, 0.0);  // (M^T M)^(-1/2)
+        std::vector<double> Ris(dd, 0.0);  // (M^T M)^(-1/2)
         const double top = std::max(w[0], 0.0);
         for (int c = 0; c < d; ++c) {
             if (!(w[c] > 1e-24 * top) || w[c] <= 0.0) continue;
@@ -252,14 +357,27 @@ extern "C" int fjofc_init_cmds(fjofc_ctx *ctx, const float *const *delta, int m,
                 for (int e = 0; e < d; ++e)
                     Ris[(size_t)a * d + e] += S[(size_t)a * d + c] * sc * S[(size_t)e * d + c];
         }
-        std::vector<double> Q((size_t)d * d, 0.0);
+        double *Q = Qall.data() + i * dd;
         for (int a = 0; a < d; ++a)
             for (int c = 0; c < d; ++c)
                 for (int r = 0; r < d; ++r) Q[(size_t)a * d + c] += Mq[(size_t)a * d + r] * Ris[(size_t)r * d + c];
-        std::memcpy(b.pin, Q.data(), sizeof(double) * d * d);
-        INIT_TRY(hipMemcpyAsync(b.small, b.pin, sizeof(double) * d * d, hipMemcpyHostToDevice, s));
-        INIT_TRY(launch_apply(b.xi, d, d, nullptr, b.small, d, n, X + (size_t)i * n * d, d, d, s));
-        INIT_TRY(hipStreamSynchronize(s));
     }
+    std::memcpy(b.pin, Qall.data(), sizeof(double) * dd * m);
+    INIT_TRY(hipMemcpyAsync(b.small, b.pin, sizeof(double) * dd * m, hipMemcpyHostToDevice, s));
+    ApplyArgs aa{};
+    aa.in = b.xi + nd;
+    aa.ldi = d;
+    aa.nin = d;
+    aa.sin = nd;
+    aa.M = b.small;
+    aa.sM = dd;
+    aa.ncol = d;
+    aa.n = n;
+    aa.out = X;
+    aa.ldo = d;
+    aa.ldo_pad = d;
+    aa.sout = nd;
+    INIT_TRY(launch_apply(aa, m, s));
+    INIT_TRY(hipStreamSynchronize(s));
     return FJOFC_OK;
 }

@@ -33,6 +33,7 @@
 // per lane across groups, one FP64 value per tile.
 #include "fjofc_internal.h"
 #include <float.h>
+#include <type_traits>
 
 namespace fjofc {
 namespace {
@@ -56,6 +57,15 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 // through the constant address space lets wave-uniform reads (a group's row
 // points) compile to scalar loads.
 typedef const __attribute__((address_space(4))) float cfloat;
+// LDS pointers carry their address space explicitly, so that code taking
+// them compiles to LDS instructions also where it is not inlined into the
+// kernel that owns the LDS (the persistent batch calls its tile code; a
+// generic pointer there would make every LDS access a flat instruction,
+// which also waits for the outstanding global loads).
+typedef __attribute__((address_space(3))) float lfloat;
+typedef __attribute__((address_space(3))) double ldouble;
+typedef __attribute__((address_space(3))) f4v lf4v;
+__device__ __forceinline__ lfloat *to_lds(float *p) { return (lfloat *)p; }
 
 // DPP controls (gfx9 encoding)
 constexpr int DPP_QP_XOR1 = 0xB1;        // quad_perm [1,0,3,2]
@@ -92,9 +102,9 @@ __device__ __forceinline__ void wave_sync() {
 // order by odd ob so the two halves of a read fall in disjoint banks), and
 // three DPP steps add the eight chunks, leaving the sum in all eight lanes
 // of the group; lane c of the group stores output ob T + c.
-template <int D>
-__device__ __forceinline__ void reduce4_lds(const float (&p)[4][D], float *red, int lane,
-                                            float *rsink, int rpitch, int rbase, int nvalid) {
+template <int D, class SINK>
+__device__ __forceinline__ void reduce4_lds(const float (&p)[4][D], lfloat *red, int lane,
+                                            SINK *rsink, int rpitch, int rbase, int nvalid) {
     constexpr int V = 4 * D, T = (V + 7) / 8;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
@@ -107,8 +117,8 @@ __device__ __forceinline__ void reduce4_lds(const float (&p)[4][D], float *red, 
 #pragma unroll
     for (int t = 0; t < T; ++t) {
         const int o = min(ob * T + t, V - 1);
-        const float4 a = *reinterpret_cast<const float4 *>(red + o * WAVE + 8 * c + h0);
-        const float4 b = *reinterpret_cast<const float4 *>(red + o * WAVE + 8 * c + (4 - h0));
+        const f4v a = *reinterpret_cast<const lf4v *>(red + o * WAVE + 8 * c + h0);
+        const f4v b = *reinterpret_cast<const lf4v *>(red + o * WAVE + 8 * c + (4 - h0));
         s[t] = ((a.x + a.y) + (a.z + a.w)) + ((b.x + b.y) + (b.z + b.w));
     }
     wave_sync();
@@ -163,20 +173,44 @@ __device__ __forceinline__ void load_rows(float (&dv)[G][CPL],
 // Terms of G rows (given in dv) against the lane's CPL columns.  The G row
 // sums go to rsink[k * rpitch + rbase + g0 + row], four rows at a time
 // through the wavefront's LDS buffer red.
-template <int D, int CPL, int G, bool VEC4, bool MASK, bool STRESS, bool ACC>
+template <int D, int CPL, int G, bool VEC4, bool MASK, bool STRESS, bool ACC, bool COH,
+          class SINK>
 __device__ __forceinline__ void process_group(
     const float (&dv)[G][CPL], const float *__restrict__ X, int n, int npad,
     int r0, int c0, int g0, int nr, int lane, const float (&xc)[CPL][D],
-    float (&cacc)[CPL][D], float *rsink, int rpitch, int rbase, float *red, double &fid) {
+    float (&cacc)[CPL][D], SINK *rsink, int rpitch, int rbase, lfloat *red, double &fid) {
     static_assert(G % 4 == 0, "rows are reduced four at a time");
     const int nv = MASK ? min(G, nr - g0) : G;
-    // the group's row points (wave-uniform scalar loads; padding rows are 0)
+    // the group's row points (wave-uniform; padding rows are 0).  Within
+    // one launch of the lockstep path the configuration is read-only, so
+    // they are scalar loads through the constant address space.  In the
+    // persistent batch (COH) the configuration is rewritten during the
+    // launch, where the scalar cache would not see the new values: there
+    // they are vector loads (after the task's acquire fence) made
+    // wave-uniform with readfirstlane.
     float xr[G][D];
-    cfloat *Xc = (cfloat *)X;
+    if constexpr (COH) {
+        // lane rr D + k loads X[k][row rr] once; readlane makes each uniform
+        static_assert(G * D <= WAVE, "a group's row points fit one wavefront");
+        float mine = 0.f;
+        if (lane < G * D) {
+            const int rr = lane / D, k = lane - rr * D;
+            mine = __hip_atomic_load(X + (size_t)k * npad + r0 + g0 + rr, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
 #pragma unroll
-    for (int k = 0; k < D; ++k)
+        for (int k = 0; k < D; ++k)
 #pragma unroll
-        for (int rr = 0; rr < G; ++rr) xr[rr][k] = Xc[(size_t)k * npad + r0 + g0 + rr];
+            for (int rr = 0; rr < G; ++rr)
+                xr[rr][k] = __int_as_float(
+                    __builtin_amdgcn_readlane(__float_as_int(mine), rr * D + k));
+    } else {
+        cfloat *Xc = (cfloat *)X;
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+#pragma unroll
+            for (int rr = 0; rr < G; ++rr) xr[rr][k] = Xc[(size_t)k * npad + r0 + g0 + rr];
+    }
     float p[G][D];
 #pragma unroll
     for (int rr = 0; rr < G; ++rr)
@@ -246,11 +280,11 @@ __device__ __forceinline__ void process_group(
 // column.  MASK is set for boundary tiles: those crossing the diagonal (only
 // l > j counts) or the ragged edge (rows or columns >= n).
 template <int D, int CPL, int G, bool DBUF, bool VEC4, bool MASK, bool STRESS, bool ACC, int R,
-          int C>
+          int C, bool COH = false>
 __device__ __forceinline__ void stream_tile(
     const TriGeom &g, const DeltaPtrs &dp, const float *__restrict__ Xs,
     int i, int I, int J, int ftile, float *__restrict__ P,
-    double *__restrict__ F, float *smem) {
+    double *__restrict__ F, lfloat *smem) {
     constexpr int NW = R * C, TWW = WAVE * CPL;
     const int lane = threadIdx.x & (WAVE - 1);
     const int w = NW == 1 ? 0 : __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
@@ -297,16 +331,23 @@ __device__ __forceinline__ void stream_tile(
     // LDS layout (several wavefronts): row sums [C][D][th], column sums
     // [R][D][tw], then one double per wavefront for the fidelity.
     const int tw = C * TWW;
-    float *srow = smem, *scol = smem + (size_t)C * D * g.th;
-    double *sfid = reinterpret_cast<double *>(scol + (size_t)R * D * tw);
-    float *rsink = NW == 1 ? prow : srow + (size_t)wc * D * g.th;
+    lfloat *srow = smem, *scol = smem + (size_t)C * D * g.th;
+    ldouble *sfid = reinterpret_cast<ldouble *>(scol + (size_t)R * D * tw);
+    // row sums go to the partial buffer (global) with one wavefront, else
+    // to LDS
+    using RS = std::conditional_t<NW == 1, float, lfloat>;
+    RS *rsink;
+    if constexpr (NW == 1)
+        rsink = prow;
+    else
+        rsink = srow + (size_t)wc * D * g.th;
     const int rpitch = NW == 1 ? npad : g.th;
     const int rbase = NW == 1 ? r0 : wr * thw;
     // this wavefront's row-reduction buffer [4 D][64]: the whole LDS with one
     // wavefront, else a slice of the column-sum region, which takes column
     // sums only after every wavefront's stream has finished
     static_assert(NW == 1 || CPL >= 4, "the reduction buffers fit the column region");
-    float *red = NW == 1 ? smem : scol + (size_t)w * 4 * D * WAVE;
+    lfloat *red = NW == 1 ? smem : scol + (size_t)w * 4 * D * WAVE;
 
     if (NW > 1 && ACC && empty) {
         // the workgroup still adds this wavefront's row sums for the rows
@@ -325,14 +366,14 @@ __device__ __forceinline__ void stream_tile(
         for (int g0 = 0; g0 < nr; g0 += 2 * G) {
             if (g0 + G < nr)
                 load_rows<CPL, G, VEC4, MASK>(db, dl, n, r0 + g0 + G, c0, lane, nr - g0 - G);
-            process_group<D, CPL, G, VEC4, MASK, STRESS, ACC>(da, X, n, npad, r0, c0, g0, nr,
+            process_group<D, CPL, G, VEC4, MASK, STRESS, ACC, COH, RS>(da, X, n, npad, r0, c0, g0, nr,
                                                               lane, xc, cacc, rsink, rpitch,
                                                               rbase, red, fid);
             if (g0 + G >= nr) break;
             if (g0 + 2 * G < nr)
                 load_rows<CPL, G, VEC4, MASK>(da, dl, n, r0 + g0 + 2 * G, c0, lane,
                                               nr - g0 - 2 * G);
-            process_group<D, CPL, G, VEC4, MASK, STRESS, ACC>(db, X, n, npad, r0, c0, g0 + G,
+            process_group<D, CPL, G, VEC4, MASK, STRESS, ACC, COH, RS>(db, X, n, npad, r0, c0, g0 + G,
                                                               nr, lane, xc, cacc, rsink, rpitch,
                                                               rbase, red, fid);
         }
@@ -341,7 +382,7 @@ __device__ __forceinline__ void stream_tile(
         for (int g0 = 0; g0 < nr; g0 += G) {
             float da[G][CPL];
             load_rows<CPL, G, VEC4, MASK>(da, dl, n, r0 + g0, c0, lane, nr - g0);
-            process_group<D, CPL, G, VEC4, MASK, STRESS, ACC>(da, X, n, npad, r0, c0, g0, nr,
+            process_group<D, CPL, G, VEC4, MASK, STRESS, ACC, COH, RS>(da, X, n, npad, r0, c0, g0, nr,
                                                               lane, xc, cacc, rsink, rpitch,
                                                               rbase, red, fid);
         }
@@ -349,16 +390,22 @@ __device__ __forceinline__ void stream_tile(
     if constexpr (NW > 1) __syncthreads();
     if (ACC) {
         // this wavefront's column sums: to the partial buffer, or to LDS
-        float *csink = NW == 1 ? pcol + c0 : scol + (size_t)wr * D * tw + wc * TWW;
+        using CS = std::conditional_t<NW == 1, float, lfloat>;
+        using CS4 = std::conditional_t<NW == 1, f4v, lf4v>;
+        CS *csink;
+        if constexpr (NW == 1)
+            csink = pcol + c0;
+        else
+            csink = scol + (size_t)wr * D * tw + wc * TWW;
         const int cpitch = NW == 1 ? npad : tw;
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             if (VEC4) {
 #pragma unroll
                 for (int h = 0; h < CPL / 4; ++h)
-                    *reinterpret_cast<float4 *>(csink + (size_t)k * cpitch + h * 256 + lane * 4) =
-                        make_float4(cacc[4 * h][k], cacc[4 * h + 1][k], cacc[4 * h + 2][k],
-                                    cacc[4 * h + 3][k]);
+                    *reinterpret_cast<CS4 *>(csink + (size_t)k * cpitch + h * 256 + lane * 4) =
+                        f4v{cacc[4 * h][k], cacc[4 * h + 1][k], cacc[4 * h + 2][k],
+                            cacc[4 * h + 3][k]};
             } else {
 #pragma unroll
                 for (int q = 0; q < CPL; ++q)
@@ -420,10 +467,10 @@ __global__ __launch_bounds__(WAVE * R * C) void bx_kernel(
     const int I = it.tile >> 16, J = it.tile & 0xffff;
     if (it.ftile < b.g.nint)
         stream_tile<D, CPL, G, DBUF, VEC4, false, STRESS, ACC, R, C>(b.g, b.dp, Xs, it.mod, I, J,
-                                                                     it.ftile, b.P, b.F, smem);
+                                                                     it.ftile, b.P, b.F, to_lds(smem));
     else
         stream_tile<D, CPL, G, DBUF, VEC4, true, STRESS, ACC, R, C>(b.g, b.dp, Xs, it.mod, I, J,
-                                                                    it.ftile, b.P, b.F, smem);
+                                                                    it.ftile, b.P, b.F, to_lds(smem));
 }
 
 // ---------------------------------------------------------------------------
@@ -460,66 +507,42 @@ __device__ __forceinline__ double slot_sum(const float *__restrict__ p, size_t s
     return (a0 + a1) + (a2 + a3);
 }
 
-// FIN_SLICES threads per (row j, component k): slice s sums the slots
-// congruent to s mod FIN_SLICES; slice 0 adds the slices in order and does
-// the FP64 combine.
+// Row j's partial sums of component k in modality q over the slots
+// congruent to sl mod FIN_SLICES: its column sums (one tile of every row
+// block I' <= j / th) minus its row sums (tiles (I, J), J < row_tiles(I)).
+// A row block whose only row is n - 1 holds no pair and has no tiles.
 constexpr int FIN_SLICES = 2;
-template <int MM>
-__global__ __launch_bounds__(FIN_ROWS *FIN_SLICES) void finalize_kernel(
-    const InstDesc *__restrict__ insts, const RowItem *__restrict__ rows, int cur,
-    int want_com) {
-    __shared__ double part[FIN_SLICES][FIN_ROWS];
-    __shared__ double sh[FIN_ROWS * FIN_SLICES / WAVE];
-    const RowItem ri = rows[blockIdx.x];
-    const InstDesc &b = insts[ri.inst];
-    if (b.st->done) return;
+__device__ __forceinline__ double fin_slice(const InstDesc &b, int q, int k, int j, int sl) {
     const TriGeom &g = b.g;
-    const int D = b.D, k = ri.k;
-    const int m = g.m, npad = g.npad, ntc = g.ntc;
+    if (j >= g.n) return 0.0;
+    const int I = j / g.th;
+    const bool live = g.n - 1 > I * g.th;
+    const int jhi = live ? row_tiles(g, I) : 0;
+    const int ihi = I + (live ? 1 : 0);
+    const size_t slot = (size_t)b.D * g.npad;
     const int S = g.ntc + g.ntr;
-    const float *__restrict__ P = b.P;
-    const double *__restrict__ Winv = b.Winv;
-    const double *__restrict__ wmat = b.wmat;
+    const float *Pb = b.P + (size_t)q * S * slot + (size_t)k * g.npad + j;
+    return slot_sum(Pb, slot, g.ntc + sl, g.ntc + ihi, FIN_SLICES) -
+           slot_sum(Pb, slot, sl, jhi, FIN_SLICES);
+}
+
+// eq:update for row j, component k from bx[q] = w_qq (B_q X^(q))_jk: writes
+// X_{t+1} (relaxed when alpha != 1) and returns the row's weighted
+// commensurability term when want_com; rows in [n, npad) get 0.
+template <int MM>
+__device__ __forceinline__ double fin_combine(const InstDesc &b, int k, int j, int cur,
+                                              const double (&bx)[MM], int want_com) {
+    const TriGeom &g = b.g;
+    const int m = g.m, D = b.D, npad = g.npad;
     float *__restrict__ Xout = b.Xs[cur ^ 1];
-    const int r = threadIdx.x % FIN_ROWS, sl = threadIdx.x / FIN_ROWS;
-    const int j = ri.bx * FIN_ROWS + r;
-    // tiles holding j as a row: (I, J) for J in [0, row_tiles(I)); as a
-    // column: one tile of every row block I' <= j / th (the tiles of a row
-    // block start on its diagonal and cover the columns after it).
-    // A row block whose only row is n - 1 holds no pair and has no tiles.
-    int jhi = 0, ihi = 0;
-    if (j < g.n) {
-        const int I = j / g.th;
-        const bool live = g.n - 1 > I * g.th;
-        jhi = live ? row_tiles(g, I) : 0;
-        ihi = I + (live ? 1 : 0);
-    }
-    const size_t slot = (size_t)D * npad;
-    double bx[MM];
-    for (int q = 0; q < m; ++q) {
-        double sq = 0.0;
-        if (j < g.n) {
-            const float *Pb = P + (size_t)q * S * slot + (size_t)k * npad + j;
-            sq = slot_sum(Pb, slot, ntc + sl, ntc + ihi, FIN_SLICES) -
-                 slot_sum(Pb, slot, sl, jhi, FIN_SLICES);
-        }
-        part[sl][r] = sq;
-        __syncthreads();
-        if (sl == 0) {
-            double t = part[0][r];
-            for (int e = 1; e < FIN_SLICES; ++e) t += part[e][r];
-            bx[q] = wmat[q * m + q] * t;
-        }
-        __syncthreads();
-    }
     double com = 0.0;
-    if (sl == 0 && j < g.n) {
+    if (j < g.n) {
         float xn[MM];
         const double alpha = b.alpha;
         const float *__restrict__ Xin = b.Xs[cur];
         for (int a = 0; a < m; ++a) {
             double v = 0.0;
-            for (int q = 0; q < m; ++q) v += Winv[a * m + q] * bx[q];
+            for (int q = 0; q < m; ++q) v += b.Winv[a * m + q] * bx[q];
             if (alpha != 1.0) {
                 // relaxed update: X_t + alpha (Gamma(X_t) - X_t)
                 const double xt = (double)Xin[((size_t)a * D + k) * npad + j];
@@ -532,14 +555,44 @@ __global__ __launch_bounds__(FIN_ROWS *FIN_SLICES) void finalize_kernel(
             for (int a = 0; a < m; ++a)
                 for (int q = a + 1; q < m; ++q) {
                     const double t = (double)xn[a] - (double)xn[q];
-                    com += wmat[a * m + q] * t * t;
+                    com += b.wmat[a * m + q] * t * t;
                 }
-    } else if (sl == 0 && j < npad) {
+    } else if (j < npad) {
         for (int a = 0; a < m; ++a) Xout[((size_t)a * D + k) * npad + j] = 0.f;
     }
+    return com;
+}
+
+// FIN_SLICES threads per (row j, component k): slice s sums the slots
+// congruent to s mod FIN_SLICES; slice 0 adds the slices in order and does
+// the FP64 combine.
+template <int MM>
+__global__ __launch_bounds__(FIN_ROWS *FIN_SLICES) void finalize_kernel(
+    const InstDesc *__restrict__ insts, const RowItem *__restrict__ rows, int cur,
+    int want_com) {
+    __shared__ double part[FIN_SLICES][FIN_ROWS];
+    __shared__ double sh[FIN_ROWS * FIN_SLICES / WAVE];
+    const RowItem ri = rows[blockIdx.x];
+    const InstDesc &b = insts[ri.inst];
+    if (b.st->done) return;
+    const int k = ri.k, m = b.g.m;
+    const int r = threadIdx.x % FIN_ROWS, sl = threadIdx.x / FIN_ROWS;
+    const int j = ri.bx * FIN_ROWS + r;
+    double bx[MM];
+    for (int q = 0; q < m; ++q) {
+        part[sl][r] = fin_slice(b, q, k, j, sl);
+        __syncthreads();
+        if (sl == 0) {
+            double t = part[0][r];
+            for (int e = 1; e < FIN_SLICES; ++e) t += part[e][r];
+            bx[q] = b.wmat[q * m + q] * t;
+        }
+        __syncthreads();
+    }
+    const double com = sl == 0 ? fin_combine<MM>(b, k, j, cur, bx, want_com) : 0.0;
     if (want_com) {
         const double s = block_sum_d(com, sh);
-        if (threadIdx.x == 0) b.comP[(size_t)k * (npad / FIN_ROWS) + ri.bx] = s;
+        if (threadIdx.x == 0) b.comP[(size_t)k * (b.g.npad / FIN_ROWS) + ri.bx] = s;
     }
 }
 
@@ -567,15 +620,15 @@ __global__ __launch_bounds__(FIN_ROWS) void com_kernel(
 
 // Deterministic FP64 reduction of the per-tile fidelity partials (weighted
 // by w_ii) and the commensurability partials, then Algorithm 2's stop test.
-// One workgroup per instance.
+// One workgroup of RED_BLOCK threads per instance.  The loop state is read
+// with atomic loads: in the persistent batch other workgroups rewrite it
+// during the launch.
 constexpr int RED_BLOCK = 256;
-__global__ __launch_bounds__(RED_BLOCK) void reduce_kernel(
-    const InstDesc *__restrict__ insts, int t, int check, int final_pass, int iters,
-    double tol, int tol_mode) {
+__device__ __forceinline__ void reduce_body(const InstDesc &b, int t, int check, int final_pass,
+                                            int iters, double tol, int tol_mode) {
     __shared__ double shf[RED_BLOCK], shc[RED_BLOCK];
-    const InstDesc &b = insts[blockIdx.x];
     EmbedState *st = b.st;
-    if (st->done) return;
+    if (__hip_atomic_load(&st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     const int tid = threadIdx.x;
     const int m = b.g.m, ntiles = b.g.nint + b.g.nbnd;
     double f = 0.0, c = 0.0;
@@ -598,27 +651,36 @@ __global__ __launch_bounds__(RED_BLOCK) void reduce_kernel(
     if (tid == 0) {
         const double fid = shf[0], com = shc[0], sigma = fid + com;
         const double mn = (double)m * b.g.n;
+        const double last = __hip_atomic_load(&st->last, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (b.hist) b.hist[t] = sigma;
         st->sigma = sigma;
         st->fid = fid;
         st->com = com;
+        bool stopped = false;
         if (check && tol > 0.0) {
             bool stop;
             if (tol_mode == 3) {
                 stop = sigma <= tol;  // stress target
             } else {
-                const double thr = (tol_mode == 2) ? tol * 0.5 * mn * (mn - 1.0) : tol * st->last;
-                stop = t > 0 && st->last - sigma < thr;
+                const double thr = (tol_mode == 2) ? tol * 0.5 * mn * (mn - 1.0) : tol * last;
+                stop = t > 0 && last - sigma < thr;
             }
             if (stop) {
                 st->done = 1;
                 st->converged = 1;
                 st->iters_run = t;
+                stopped = true;
             }
         }
         if (check) st->last = sigma;
-        if (final_pass && !st->converged) st->iters_run = iters;
+        if (final_pass && !stopped) st->iters_run = iters;
     }
+}
+
+__global__ __launch_bounds__(RED_BLOCK) void reduce_kernel(
+    const InstDesc *__restrict__ insts, int t, int check, int final_pass, int iters,
+    double tol, int tol_mode) {
+    reduce_body(insts[blockIdx.x], t, check, final_pass, iters, tol, tol_mode);
 }
 
 // Per instance: reset the loop state, fill the history with NaN, convert X0
@@ -677,6 +739,248 @@ __global__ void to_soa_kernel(TriGeom g, int D, const float *__restrict__ X,
     for (int k = 0; k < D; ++k)
         Xs[((size_t)a * D + k) * g.npad + j] =
             (j < g.n) ? X[((size_t)a * g.n + j) * D + k] : 0.f;
+}
+
+// ---------------------------------------------------------------------------
+// Persistent batched launch (see BatchArgs): every transform of every
+// problem in one launch, tasks taken from a queue in a fixed order, each
+// waiting (bounded) on per-problem completion counters.
+// ---------------------------------------------------------------------------
+
+// One tile of a stream group: the same code as the lockstep kernel (results
+// are bitwise equal), with the row points read coherently.  One-wavefront
+// tiles (variant 1) run on the calling wavefront and its LDS slice, shared
+// tiles (variants 4 and 5) on the whole workgroup.
+template <int D, int VAR, bool VEC4, bool STRESS>
+__device__ __forceinline__ void batch_tile(const InstDesc *__restrict__ insts,
+                                           const StreamItem &it, int cur, lfloat *smem) {
+    constexpr int R = VAR == 4 ? 4 : (VAR == 5 ? 2 : 1);
+    constexpr int C = VAR == 5 ? 2 : 1;
+    const InstDesc &b = insts[it.inst];
+    const float *Xs = b.Xs[cur];
+    const int I = it.tile >> 16, J = it.tile & 0xffff;
+    if (it.ftile < b.g.nint)
+        stream_tile<D, 4, 8, false, VEC4, false, STRESS, true, R, C, true>(
+            b.g, b.dp, Xs, it.mod, I, J, it.ftile, b.P, b.F, smem);
+    else
+        stream_tile<D, 4, 8, false, VEC4, true, STRESS, true, R, C, true>(
+            b.g, b.dp, Xs, it.mod, I, J, it.ftile, b.P, b.F, smem);
+}
+
+// A stream group: `count` tiles of one problem.  One-wavefront tiles:
+// wavefront w takes tiles w, w + 4, ...  Shared tiles: the workgroup takes
+// them in turn, with a barrier between two (the next tile reuses the LDS
+// the last one's epilogue reads).
+template <int D, int VAR, bool VEC4, bool STRESS>
+__device__ __forceinline__ void batch_stream(const InstDesc *__restrict__ insts,
+                                             const StreamItem *__restrict__ items, int count,
+                                             int cur, lfloat *smem) {
+    if constexpr (VAR == 1) {
+        const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+        lfloat *ws = smem + (size_t)w * 4 * D * WAVE;
+        for (int q = w; q < count; q += BATCH_BLOCK / WAVE)
+            batch_tile<D, VAR, VEC4, STRESS>(insts, items[q], cur, ws);
+    } else {
+        for (int q = 0; q < count; ++q) {
+            if (q > 0) __syncthreads();
+            batch_tile<D, VAR, VEC4, STRESS>(insts, items[q], cur, smem);
+        }
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void batch_stream_d(int variant, int vec4, bool stress,
+                                               const InstDesc *insts, const StreamItem *items,
+                                               int count, int cur, lfloat *smem) {
+#define FJOFC_BS(V, V4, S)                                                          \
+    if (variant == V && (vec4 != 0) == V4 && stress == S)                           \
+        return batch_stream<D, V, V4, S>(insts, items, count, cur, smem);
+    FJOFC_BS(1, false, false) FJOFC_BS(1, false, true) FJOFC_BS(1, true, false)
+    FJOFC_BS(1, true, true) FJOFC_BS(4, false, false) FJOFC_BS(4, false, true)
+    FJOFC_BS(4, true, false) FJOFC_BS(4, true, true) FJOFC_BS(5, false, false)
+    FJOFC_BS(5, false, true) FJOFC_BS(5, true, false) FJOFC_BS(5, true, true)
+#undef FJOFC_BS
+}
+
+template <int MAXD>
+__device__ __forceinline__ void batch_stream_any(int D, int variant, int vec4, bool stress,
+                                                 const InstDesc *insts, const StreamItem *items,
+                                                 int count, int cur, lfloat *smem) {
+    switch (D) {
+    case 1: if constexpr (MAXD >= 1) batch_stream_d<1>(variant, vec4, stress, insts, items, count, cur, smem); break;
+    case 2: if constexpr (MAXD >= 2) batch_stream_d<2>(variant, vec4, stress, insts, items, count, cur, smem); break;
+    case 3: if constexpr (MAXD >= 3) batch_stream_d<3>(variant, vec4, stress, insts, items, count, cur, smem); break;
+    case 4: if constexpr (MAXD >= 4) batch_stream_d<4>(variant, vec4, stress, insts, items, count, cur, smem); break;
+    case 5: if constexpr (MAXD >= 5) batch_stream_d<5>(variant, vec4, stress, insts, items, count, cur, smem); break;
+    case 6: if constexpr (MAXD >= 6) batch_stream_d<6>(variant, vec4, stress, insts, items, count, cur, smem); break;
+    case 7: if constexpr (MAXD >= 7) batch_stream_d<7>(variant, vec4, stress, insts, items, count, cur, smem); break;
+    case 8: if constexpr (MAXD >= 8) batch_stream_d<8>(variant, vec4, stress, insts, items, count, cur, smem); break;
+    default: break;
+    }
+}
+
+// One finalize row item: rows [bx 256, bx 256 + 256) and component k, one
+// row per thread, each thread summing both slot slices in the lockstep
+// finalize's order, so the results are bitwise equal to it.
+template <int MM>
+__device__ __forceinline__ void batch_fin_row(const InstDesc &b, RowItem ri, int cur,
+                                              int want_com, double *sh) {
+    const int k = ri.k, m = b.g.m;
+    const int j = ri.bx * FIN_ROWS + threadIdx.x;
+    double bx[MM];
+    for (int q = 0; q < m; ++q) {
+        double t = fin_slice(b, q, k, j, 0);
+        for (int e = 1; e < FIN_SLICES; ++e) t += fin_slice(b, q, k, j, e);
+        bx[q] = b.wmat[q * m + q] * t;
+    }
+    const double com = fin_combine<MM>(b, k, j, cur, bx, want_com);
+    if (want_com) {
+        const double s = block_sum_d(com, sh);
+        if (threadIdx.x == 0) b.comP[(size_t)k * (b.g.npad / FIN_ROWS) + ri.bx] = s;
+    }
+}
+
+// A finalize group: `count` row items of one problem in turn (a barrier
+// between two: the block sums reuse sh).
+template <int MM>
+__device__ __forceinline__ void batch_fin(const InstDesc &b, const RowItem *__restrict__ rows,
+                                          int count, int cur, int want_com, double *sh) {
+    for (int q = 0; q < count; ++q) {
+        if (q > 0) __syncthreads();
+        batch_fin_row<MM>(b, rows[q], cur, want_com, sh);
+    }
+}
+
+// Bounded wait until *p >= need, run by a whole wavefront (every lane
+// loads the same counter; the value is made wave-uniform, so the loop is
+// uniform).  Gives up when another workgroup has flagged an error, or after
+// a.timeout wall-clock ticks, flagging one itself: the launch then drains
+// instead of hanging.
+__device__ __forceinline__ int uniform_load(int *p) {
+    return __builtin_amdgcn_readfirstlane(
+        __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+__device__ __forceinline__ bool batch_wait(const BatchArgs &a, int *p, int need) {
+    if (uniform_load(p) >= need) return true;
+    const long long t0 = (long long)wall_clock64();
+    for (;;) {
+        __builtin_amdgcn_s_sleep(2);
+        if (uniform_load(p) >= need) return true;
+        if (uniform_load(a.err)) return false;
+        if ((long long)wall_clock64() - t0 > a.timeout) {
+            __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+    }
+}
+
+// The reduce task (a noinline call keeps its per-thread branches out of the
+// persistent loop's control flow).
+__device__ __noinline__ void batch_red(const InstDesc *__restrict__ insts, int inst, int t,
+                                       int check, int final_pass, int iters, double tol,
+                                       int tol_mode) {
+    reduce_body(insts[inst], t, check, final_pass, iters, tol, tol_mode);
+}
+
+// The task loop has no lane-divergent branch: the queue and the counters
+// are handled by the whole of wavefront 0 (a wave-uniform branch), whose
+// lanes all compute the same values; the atomics add 1 from lane 0 and 0
+// from the others.  The values published through LDS are read back
+// wave-uniform.  (With lane-divergent branches at the loop's head and tail
+// the compiler may restructure it into nested loops in which the other
+// lanes of wavefront 0 reach the next barrier before lane 0 has fetched
+// the next task.)
+template <int MAXD>
+__global__ __launch_bounds__(BATCH_BLOCK)
+__attribute__((amdgpu_waves_per_eu(MAXD <= 5 ? 4 : 2, 8))) void batch_kernel(BatchArgs a) {
+    extern __shared__ float smem[];
+    __shared__ long long sh_q;
+    __shared__ int sh_state;
+    __shared__ double sh_fin[BATCH_BLOCK / WAVE];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int one = (threadIdx.x & (WAVE - 1)) == 0 ? 1 : 0;
+    for (;;) {
+        if (wave == 0) {
+            const unsigned long long o = atomicAdd(
+                reinterpret_cast<unsigned long long *>(a.head), (unsigned long long)one);
+            long long q = (long long)(((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane(
+                                           (int)(o >> 32)) << 32) |
+                                      (unsigned)__builtin_amdgcn_readfirstlane((int)o));
+            if (uniform_load(a.err)) q = a.ntasks;
+            sh_q = q;
+        }
+        __syncthreads();
+        const long long q = (long long)(((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane(
+                                              (int)((unsigned long long)sh_q >> 32)) << 32) |
+                                        (unsigned)__builtin_amdgcn_readfirstlane((int)sh_q));
+        if (q >= a.ntasks) break;
+        int t, pos;
+        batch_task_at(q, a.L, t, pos);
+        const BatchTask tk = a.tmpl[pos];
+        const InstDesc &b = a.insts[tk.inst];
+        int *c = &a.ctr[tk.inst].s_done;  // s_done, r_done, f_done
+        const BatchDep dep = batch_dep(tk.kind, t, b.bnst, b.bnfin);
+        int *wc = c + dep.wait, *dc = c + dep.done, need = dep.need;
+        if (a.never_wait && q == 0) {
+            wc = a.never;
+            need = 1;
+        }
+        if (wave == 0) {
+            const bool ok = batch_wait(a, wc, need);
+            // acquire at agent scope: the producers' writes (released by
+            // their workgroups, possibly on other XCDs) are visible
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            sh_state = !ok ? 0 : (uniform_load(&b.st->done) ? 1 : 2);
+        }
+        __syncthreads();
+        const int state = __builtin_amdgcn_readfirstlane(sh_state);
+        if (state == 0) break;
+        const bool live = state == 2;
+        const int cur = t & 1;
+        if (tk.kind == BT_STREAM) {
+            const bool stress = (t % a.every) == 0 || t == a.iters;
+            if (live)
+                batch_stream_any<MAXD>(b.D, b.g.variant, b.g.vec4, stress, a.insts,
+                                       a.items + tk.first, tk.count, cur, to_lds(smem));
+        } else if (tk.kind == BT_RED) {
+            const bool fin = t == a.iters;
+            if (fin || (t % a.every) == 0)
+                batch_red(a.insts, tk.inst, t, fin ? ((a.iters % a.every) == 0 ? 1 : 0) : 1,
+                          fin ? 1 : 0, a.iters, a.tol, a.tol_mode);
+        } else if (live) {
+            const int want_com = ((t + 1) % a.every) == 0 || (t + 1) == a.iters;
+            const RowItem *rows = a.rows + tk.first;
+            if (b.g.m <= 4)
+                batch_fin<4>(b, rows, tk.count, cur, want_com, sh_fin);
+            else if (b.g.m <= 8)
+                batch_fin<8>(b, rows, tk.count, cur, want_com, sh_fin);
+            else
+                batch_fin<MAXM>(b, rows, tk.count, cur, want_com, sh_fin);
+        }
+        __syncthreads();
+        if (wave == 0) {
+            // release at agent scope: the workgroup's writes (ordered before
+            // this point by the barrier) reach the device before the count
+            // (the group's tiles, rows or one reduce)
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            atomicAdd(dc, one * tk.count);
+        }
+    }
+}
+
+__global__ void batch_reset_kernel(BatchArgs a, int count) {
+    for (int q = threadIdx.x; q < count; q += blockDim.x) {
+        a.ctr[q].s_done = 0;
+        a.ctr[q].r_done = 0;
+        a.ctr[q].f_done = 0;
+        a.ctr[q].pad = 0;
+    }
+    if (threadIdx.x == 0) {
+        *reinterpret_cast<unsigned long long *>(a.head) = 0ull;
+        *a.err = 0;
+        *a.never = 0;
+    }
 }
 
 template <int D, int CPL, int G, bool DBUF, bool VEC4, int R, int C>
@@ -782,6 +1086,46 @@ hipError_t launch_to_soa(const TriGeom &g, int D, const float *X, float *Xs,
     const size_t tot = (size_t)g.m * g.npad;
     to_soa_kernel<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(g, D, X, Xs);
     return hipGetLastError();
+}
+
+hipError_t launch_batch_reset(const BatchArgs &a, int count, hipStream_t s) {
+    batch_reset_kernel<<<1, 256, 0, s>>>(a, count);
+    return hipGetLastError();
+}
+
+namespace {
+// the D tier of a batch
+const void *batch_kernel_for(int maxd) {
+    return maxd <= 5 ? reinterpret_cast<const void *>(&batch_kernel<5>)
+                     : reinterpret_cast<const void *>(&batch_kernel<8>);
+}
+}  // namespace
+
+hipError_t launch_batch_persistent(const BatchArgs &a, int maxd, int maxm, int grid, size_t lds,
+                                   hipStream_t s) {
+    (void)maxm;
+    if (grid < 1) return hipErrorInvalidValue;
+    const dim3 g((unsigned)grid), blk(BATCH_BLOCK);
+    if (maxd <= 5)
+        batch_kernel<5><<<g, blk, lds, s>>>(a);
+    else
+        batch_kernel<8><<<g, blk, lds, s>>>(a);
+    return hipGetLastError();
+}
+
+int batch_resident_blocks(int maxd, int maxm, size_t lds) {
+    (void)maxm;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel_for(maxd), BATCH_BLOCK,
+                                                     lds) != hipSuccess)
+        return 0;
+    return nb;
+}
+
+size_t batch_stream_lds(int D, int variant, size_t tile_lds) {
+    // one-wavefront tiles: each of the four wavefronts its own [4 D][64]
+    // reduction buffer; shared tiles: the tile's own layout
+    return variant == 1 ? (size_t)(BATCH_BLOCK / WAVE) * 4 * D * WAVE * sizeof(float) : tile_lds;
 }
 
 }  // namespace fjofc

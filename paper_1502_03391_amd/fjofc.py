@@ -19,12 +19,14 @@ FJOFC_OK = 0
 FJOFC_TOL_NONE, FJOFC_TOL_REL, FJOFC_TOL_PAPER, FJOFC_TOL_TARGET = 0, 1, 2, 3
 FJOFC_MAX_M = 32
 FJOFC_MAX_D = 8
+FJOFC_LAUNCH_LOCKSTEP, FJOFC_LAUNCH_PERSISTENT = 0, 1
 
 # Every symbol include/fjofc.h declares.
 EXPORTS = ["fjofc_create", "fjofc_destroy", "fjofc_last_error", "fjofc_strerror",
            "fjofc_embed", "fjofc_embed_w", "fjofc_stress", "fjofc_oos",
            "fjofc_profile_enable", "fjofc_profile_read", "fjofc_batch_create",
-           "fjofc_batch_run", "fjofc_batch_destroy", "fjofc_embed_batched",
+           "fjofc_batch_run", "fjofc_batch_set_launch", "fjofc_tile_choice", "fjofc_batch_destroy",
+           "fjofc_embed_batched",
            "fjofc_mlp_create", "fjofc_mlp_destroy", "fjofc_mlp_set_params",
            "fjofc_mlp_get_params", "fjofc_mlp_forward", "fjofc_mlp_backward",
            "fjofc_mlp_get_grads", "fjofc_mlp_adam", "fjofc_mlp_features",
@@ -50,7 +52,9 @@ class FjofcProfile(C.Structure):
                 ("reduce_launches", C.c_int), ("reduce_ms", C.c_double),
                 ("oos_launches", C.c_int), ("oos_ms", C.c_double),
                 ("oos_bytes", C.c_double), ("batch_launches", C.c_int),
-                ("batch_ms", C.c_double), ("batch_bytes", C.c_double)]
+                ("batch_ms", C.c_double), ("batch_bytes", C.c_double),
+                ("init_launches", C.c_int), ("init_ms", C.c_double),
+                ("init_bytes", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -106,6 +110,8 @@ def lib():
         L.fjofc_oos_noalloc.argtypes = L.fjofc_oos.argtypes
         L.fjofc_batch_create.argtypes = [vp, C.POINTER(FjofcProblem), ip, C.POINTER(vp)]
         L.fjofc_batch_run.argtypes = [vp, ip, dp, ip, ip, C.POINTER(FjofcResult), vp]
+        L.fjofc_batch_set_launch.argtypes = [vp, ip]
+        L.fjofc_tile_choice.argtypes = [vp, ip, ip, C.POINTER(ip), C.POINTER(ip)]
         L.fjofc_batch_destroy.argtypes = [vp]
         L.fjofc_batch_destroy.restype = None
         L.fjofc_embed_batched.argtypes = [vp, C.POINTER(FjofcProblem), ip, ip, dp, ip, ip,
@@ -309,7 +315,7 @@ class Batch:
     problems: sequence of (delta list, wmat, X) with CUDA float32 tensors;
     the tensors are referenced, not copied, and must outlive the plan."""
 
-    def __init__(self, ctx: Context, problems):
+    def __init__(self, ctx: Context, problems, launch: str = "lockstep"):
         import torch
         self.ctx = ctx
         self._keep = []
@@ -326,6 +332,16 @@ class Batch:
         self.count = len(problems)
         self._h = C.c_void_p()
         _check(lib().fjofc_batch_create(ctx.handle, arr, self.count, C.byref(self._h)))
+        if launch != "lockstep":
+            self.set_launch(launch)
+
+    def set_launch(self, launch: str):
+        """"lockstep" (FJOFC_LAUNCH_LOCKSTEP) or "persistent"."""
+        code = {"lockstep": FJOFC_LAUNCH_LOCKSTEP, "persistent": FJOFC_LAUNCH_PERSISTENT}
+        if launch not in code:
+            raise ValueError(f"unknown batch launch {launch!r}")
+        _check(lib().fjofc_batch_set_launch(self._h, code[launch]))
+        self.launch = launch
 
     def run(self, iters: int, tol: float = 0.0, tol_mode: int = FJOFC_TOL_REL,
             stress_every: int = 1, want_results: bool = True, stream=None):
@@ -352,6 +368,17 @@ def fjofc_batch_create(ctx: Context, problems) -> Batch:
 
 def fjofc_batch_run(batch: Batch, iters: int, **kw):
     return batch.run(iters, **kw)
+
+
+def fjofc_tile_choice(ctx: Context, n: int, d: int):
+    """(tile height, kernel variant) the library plans for an (n, d) problem."""
+    th, var = C.c_int(), C.c_int()
+    _check(lib().fjofc_tile_choice(ctx.handle, int(n), int(d), C.byref(th), C.byref(var)))
+    return th.value, var.value
+
+
+def fjofc_batch_set_launch(batch: Batch, launch: str):
+    batch.set_launch(launch)
 
 
 def fjofc_batch_destroy(batch: Batch):

@@ -41,8 +41,12 @@ def _gpu_init(ctx, delta, d, iters):
 
 
 @pytest.mark.parametrize("m,n,d,lat", [(3, 400, 3, 4), (2, 257, 5, 8), (2, 120, 8, 8),
-                                       (1, 64, 2, 3), (2, 6, 2, 3)])
+                                       (1, 64, 2, 3), (2, 6, 2, 3), (4, 300, 2, 3),
+                                       (5, 97, 2, 3), (6, 160, 3, 4), (3, 1024, 5, 8)])
 def test_init_matches_dense_oracle(ctx, m, n, d, lat):
+    """m <= 4: one pass over the matrices per step forms every product
+    (n % 4 == 0 takes the 16-byte loads); m > 4: the mean's pass, then
+    modalities in groups of four (m = 5: 4 + 1, m = 6: 4 + 2)."""
     views, _, _ = gen.latent_views(80 + n, n, m, lat, 0.2, d)
     delta = [gen.pairwise_dist_np(Y).astype(np.float32) for Y in views]
     Xo, eo = dense.paper_init(delta, d)
@@ -97,3 +101,37 @@ def test_init_rejects_bad_arguments(ctx):
         fjofc.fjofc_init_cmds(ctx, dd, torch.empty((100, 9), device="cuda"))
     with pytest.raises(fjofc.FjofcError):
         fjofc.fjofc_init_cmds(ctx, dd, torch.empty((100, 2), device="cuda"), iters=0)
+
+
+def test_init_full_size_invariant_subspaces(ctx):
+    """The benchmark's in-sample workload (m = 3, n = 20000, d = 5), 40
+    steps: each block X^(i)_0 spans an invariant subspace of its
+    P_i = -1/2 J (Delta_i o Delta_i) J (the residual of P_i X^(i) off
+    span(X^(i)) is small next to P_i X^(i)), and the eigenvalues of P_i
+    restricted to that span are the returned Ritz values of Delta_i; the
+    blocks are centred.  Reference products in plain FP32 PyTorch."""
+    spec = gen.config1_spec()
+    views, _, _ = gen.config1_views(spec)
+    dev = torch.device("cuda:0")
+    delta = [gen.pairwise_dist_torch(Y, dev) for Y in views]
+    m, n, d = spec.m, spec.n, spec.d
+    X = torch.empty((m * n, d), device=dev)
+    eig = fjofc.fjofc_init_cmds(ctx, delta, X, iters=40)
+    torch.cuda.synchronize()
+    for i in range(m):
+        Xi = X[i * n:(i + 1) * n].double()
+        assert float(Xi.mean(0).abs().max()) <= 1e-4 * float(Xi.abs().max())
+        Xc = X[i * n:(i + 1) * n]
+        S = delta[i] * delta[i]
+        PX = S @ (Xc - Xc.mean(0))
+        PX = -0.5 * (PX - PX.mean(0))
+        del S
+        PX = PX.double()
+        Q, _ = torch.linalg.qr(Xi)
+        off = PX - Q @ (Q.T @ PX)
+        assert float(off.norm() / PX.norm()) <= 2e-3
+        H = torch.linalg.solve(Xi.T @ Xi, Xi.T @ PX)
+        ev = torch.linalg.eigvals(H).real.sort(descending=True).values.cpu().numpy()
+        np.testing.assert_allclose(ev, eig[1 + i], rtol=2e-3)
+    del delta
+    torch.cuda.empty_cache()
