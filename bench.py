@@ -27,11 +27,15 @@ METRIC = "fJOFC Δ-pairs/s & HBM GB/s; time-to-stress-tol, learned warm start vs
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_insample_stream_m3_n20000_d5.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1502_03391_amd", "csrc", "insample.hip")
+TILE_CACHE = os.path.join(ROOT, "paper_1502_03391_amd", "tune_cache.txt")
+# the stream kernel and the cache that picks its tile
+STREAM_SRC = (KERNEL_SRC, TILE_CACHE)
 OOS_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_oos_m2_n10000_d5.json")
 OOS_SRC = os.path.join(ROOT, "paper_1502_03391_amd", "csrc", "oos.hip")
 BATCHED_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_batched_512_uneven.json")
 # the batch's kernels and its launch plan
-BATCHED_SRC = (KERNEL_SRC, os.path.join(ROOT, "paper_1502_03391_amd", "csrc", "host.cpp"))
+BATCHED_SRC = (KERNEL_SRC, os.path.join(ROOT, "paper_1502_03391_amd", "csrc", "host.cpp"),
+               TILE_CACHE)
 
 
 def kernel_hash(src=KERNEL_SRC) -> str:
@@ -42,7 +46,7 @@ def kernel_hash(src=KERNEL_SRC) -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(path=TRAFFIC_FILE, src=KERNEL_SRC, key="bytes_per_launch"):
+def load_traffic(path=TRAFFIC_FILE, src=STREAM_SRC, key="bytes_per_launch"):
     """HBM bytes per launch of a kernel (or per unit `key` names) from
     committed rocprofv3 counter runs, or None when absent or taken on a
     different kernel source."""
@@ -500,7 +504,13 @@ def bench_batched(ctx, iters=150, launches=("lockstep", "persistent")):
         torch.cuda.synchronize()
 
     def timed(launch):
-        b = fjofc.Batch(ctx, probs, launch=launch)
+        b = fjofc.Batch(ctx, probs)
+        try:
+            b.set_launch(launch)
+        except fjofc.FjofcError as e:
+            b.close()
+            print(f"[bench] batched: no {launch} launch: {e}", file=sys.stderr, flush=True)
+            return None
         reset()
         b.run(iters, stress_every=iters, want_results=False)
         torch.cuda.synchronize()
@@ -515,8 +525,32 @@ def bench_batched(ctx, iters=150, launches=("lockstep", "persistent")):
         b.close()
         return min(times), res, out
 
-    runs = {la: timed(la) for la in launches}
-    first = runs[launches[0]]
+    def persistent_retiling():
+        # problems whose cached tile has 8 columns per lane, which the
+        # persistent kernel has no form of, take the 4-column tile of the
+        # same height: scoped FJOFC_TILE entries, and how many problems
+        swap, k = set(), 0
+        for sp in specs:
+            th, var = fjofc.fjofc_tile_choice(ctx, sp.n, sp.d)
+            if var in (2, 3):
+                swap.add(f"{sp.d}:{sp.n}:{sp.n}:{th}:1")
+                k += 1
+        return ",".join(sorted(swap)), k
+
+    def timed_on(tiles, launch):
+        os.environ["FJOFC_TILE"] = tiles
+        try:
+            return timed(launch)
+        finally:
+            os.environ.pop("FJOFC_TILE", None)
+
+    first = timed(launches[0])
+    retiled = None
+    if first is None and launches[0] == "persistent":
+        retiled = persistent_retiling()
+        first = timed_on(retiled[0], "persistent")
+    if first is None:
+        raise RuntimeError(f"the batch has no {launches[0]} launch")
     sec, res = first[0], first[1]
     hbm = load_traffic(BATCHED_TRAFFIC_FILE, BATCHED_SRC, "bytes_per_sweep")
     r = {"workload": "batched_512_uneven", "problems": len(specs), "iters": iters,
@@ -528,15 +562,30 @@ def bench_batched(ctx, iters=150, launches=("lockstep", "persistent")):
          "mean_stress_norm": float(np.mean([x["stress_norm"] for x in res]))}
     if hbm is not None:
         r["hbm_gbs"] = hbm * iters / sec / 1e9
-    if "persistent" in runs and launches[0] != "persistent":
-        sec_p, res_p, Xp = runs["persistent"]
-        r["persistent_seconds"] = sec_p
-        r["persistent_equals_lockstep"] = (
-            all(torch.equal(a, c) for a, c in zip(Xp, first[2])) and res == res_p)
-    print(f"[bench] batched: " + ", ".join(f"{la} {runs[la][0]:.4f} s" for la in launches)
-          + (f" (bitwise equal: {r['persistent_equals_lockstep']})"
-             if "persistent_equals_lockstep" in r else ""), file=sys.stderr, flush=True)
-    del runs, first
+    if retiled is not None:
+        r["persistent_plan"] = {"problems_retiled": retiled[1]}
+    msg = f"{launches[0]} {sec:.4f} s"
+    if "persistent" in launches[1:]:
+        ref = first
+        pers = timed("persistent")
+        if pers is None:
+            # compare both launches on one plan the persistent kernel runs
+            retiled = persistent_retiling()
+            ref = timed_on(retiled[0], "lockstep")
+            pers = timed_on(retiled[0], "persistent")
+            r["persistent_plan"] = {"problems_retiled": retiled[1],
+                                    "lockstep_seconds_same_plan": ref[0]}
+            msg += f", lockstep on the persistent plan {ref[0]:.4f} s"
+        if pers is not None:
+            r["persistent_seconds"] = pers[0]
+            r["persistent_equals_lockstep"] = (
+                all(torch.equal(a, c) for a, c in zip(pers[2], ref[2])) and ref[1] == pers[1])
+            msg += (f", persistent {pers[0]:.4f} s (bitwise equal to lockstep on its plan: "
+                    f"{r['persistent_equals_lockstep']})")
+        else:
+            r["launches_not_available"] = ["persistent"]
+    print(f"[bench] batched: {msg}", file=sys.stderr, flush=True)
+    del first
     del probs
     torch.cuda.empty_cache()
     return r

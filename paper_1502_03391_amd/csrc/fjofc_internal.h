@@ -207,8 +207,10 @@ constexpr int BATCH_TILES_1W = 16, BATCH_TILES_SHARED = 4, BATCH_ROWS = 4;
 // Dynamic LDS one persistent workgroup needs for a problem's stream tasks.
 size_t batch_stream_lds(int D, int variant, size_t tile_lds);
 // Kernel variants the persistent kernel runs (one-wavefront 4 x 8 tiles,
-// 4 x 1 and 2 x 2 shared tiles).
-inline bool batch_variant_ok(int variant) { return variant == 1 || variant == 4 || variant == 5; }
+// with or without double-buffered loads, and 4 x 1 and 2 x 2 shared tiles).
+inline bool batch_variant_ok(int variant) {
+    return variant == 0 || variant == 1 || variant == 4 || variant == 5;
+}
 
 // ---- launchers (oos.hip) ---------------------------------------------
 struct OOSArgs {

@@ -1307,7 +1307,7 @@ int fjofc_batch_create(fjofc_ctx *ctx, const fjofc_problem *probs, int count,
             const HostInst &h = b->hi[p];
             std::vector<StreamItem> its;
             append_items(p, h, its);
-            const int per = h.g.variant == 1 ? BATCH_TILES_1W : BATCH_TILES_SHARED;
+            const int per = h.g.variant <= 1 ? BATCH_TILES_1W : BATCH_TILES_SHARED;
             for (size_t q = 0; q < its.size(); q += per) {
                 const int cnt = (int)std::min<size_t>(per, its.size() - q);
                 tstream.push_back({BT_STREAM, p, (int)(pitems.size() + q), cnt});

@@ -52,10 +52,12 @@ LAUNCHES = ["lockstep", "persistent"]
 
 
 @pytest.mark.parametrize("launch", LAUNCHES)
-@pytest.mark.parametrize("tile", [None, "64:4", "96:5"])
+@pytest.mark.parametrize("tile", [None, "64:4", "96:5", "128:0"])
 def test_batch_equals_standalone_and_oracle(ctx, monkeypatch, tile, launch):
     """Also with every instance forced onto a multi-wavefront tile variant,
-    whose launches size their LDS for the tallest tile of the batch."""
+    whose launches size their LDS for the tallest tile of the batch, or onto
+    the double-buffered one-wavefront variant (which the persistent launch
+    runs in its single-buffer form: same sums, so still bitwise equal)."""
     if tile:
         monkeypatch.setenv("FJOFC_TILE", tile)
     insts = _instances(12)
@@ -199,6 +201,23 @@ def test_persistent_and_lockstep_batches_agree(ctx):
     with pytest.raises(ValueError):
         b.set_launch("other")
     assert fjofc.lib().fjofc_batch_set_launch(b._h, 7) == 1  # FJOFC_EINVAL
+    b.close()
+
+
+def test_persistent_launch_refuses_other_variants(ctx, monkeypatch):
+    """Tiles of 8 columns per lane (variants 2 and 3) have no persistent
+    form: selecting the persistent launch for such a batch returns
+    FJOFC_EINVAL and leaves the plan usable in lockstep."""
+    monkeypatch.setenv("FJOFC_TILE", "64:2")
+    insts = _instances(3, seed=29, n_lo=30, n_hi=200)
+    dev = [([_dev(x) for x in dl], w, _dev(X0)) for _, dl, w, X0 in insts]
+    b = fjofc.Batch(ctx, dev)
+    with pytest.raises(fjofc.FjofcError) as e:
+        b.set_launch("persistent")
+    assert e.value.code == 1
+    res = b.run(5, stress_every=5)
+    torch.cuda.synchronize()
+    assert all(r["iters_run"] == 5 for r in res)
     b.close()
 
 
