@@ -48,8 +48,11 @@ __device__ __forceinline__ void load8(const float *__restrict__ row, int l, int 
     }
 }
 
-// One wavefront: GR_ROWS rows j0.. of every problem's (A o A) V over the
-// columns [cbeg, cend) of its split, written to part.  Problems of the
+// One workgroup: GR_ROWS rows j0.. of every problem's (A o A) V over the
+// columns [cbeg, cend) of its split, written to part.  Its four wavefronts
+// take the split's 32-column steps in turn (wavefront w steps w, w + 4, ...),
+// so together they read each row 512 contiguous bytes at a time, and their
+// sums are added through LDS in a fixed order at the end.  Problems of the
 // launch: the mean (MEAN) then modalities i0 .. i0 + G - 1.  With MEAN and
 // G > 0 the launch holds all m modalities (nsrc == G) and the mean is formed
 // from the same loaded values; with G == 0 the mean sums nsrc rows itself.
@@ -61,11 +64,11 @@ __device__ __forceinline__ void load8(const float *__restrict__ row, int l, int 
 template <int G, bool MEAN, bool VEC>
 __global__ __launch_bounds__(GR_BLOCK) void gram_kernel(GramArgs a) {
     constexpr int P = G + (MEAN ? 1 : 0);
+    __shared__ f4v red[GR_RB * P][WAVE];
     const int lane = threadIdx.x & (WAVE - 1);
-    const int gw = blockIdx.x * GR_WAVES + (int)(threadIdx.x / WAVE);
-    if (gw >= a.nrowblk * a.splits) return;  // whole wavefronts; no barriers
-    const int split = gw / a.nrowblk;
-    const int rblk = gw - split * a.nrowblk;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+    const int split = blockIdx.x / a.nrowblk;
+    const int rblk = blockIdx.x - split * a.nrowblk;
     const int j0 = rblk * GR_ROWS;
     const int cbeg = split * a.cpw;
     const int cend = min(a.n, cbeg + a.cpw);
@@ -75,7 +78,7 @@ __global__ __launch_bounds__(GR_BLOCK) void gram_kernel(GramArgs a) {
     for (int rb = 0; rb < GR_RB; ++rb)
 #pragma unroll
         for (int p = 0; p < P; ++p) acc[rb][p] = f4v{0.f, 0.f, 0.f, 0.f};
-    for (int l0 = cbeg; l0 < cend; l0 += GR_CHUNK) {
+    for (int l0 = cbeg + w * GR_CHUNK; l0 < cend; l0 += GR_WAVES * GR_CHUNK) {
         const int lb = l0 + lq;
         // B operands: V_p[lb + q][c] from the transposed copy (zero-padded
         // to 16 rows and npad columns)
@@ -138,16 +141,31 @@ __global__ __launch_bounds__(GR_BLOCK) void gram_kernel(GramArgs a) {
                                                                       acc[rb][p], 0, 0, 0);
         }
     }
+    // wavefront 0's sums + ((3's + 2's) + 1's), through LDS
+    for (int src = GR_WAVES - 1; src >= 1; --src) {
+        if (w == src) {
+#pragma unroll
+            for (int rb = 0; rb < GR_RB; ++rb)
+#pragma unroll
+                for (int p = 0; p < P; ++p)
+                    red[rb * P + p][lane] = src == GR_WAVES - 1
+                                                ? acc[rb][p]
+                                                : red[rb * P + p][lane] + acc[rb][p];
+        }
+        __syncthreads();
+    }
+    if (w != 0) return;
     // partial results: part[split][pbase + p][row][16]
     const int rq = 4 * (lane >> 4);
 #pragma unroll
     for (int rb = 0; rb < GR_RB; ++rb)
 #pragma unroll
         for (int p = 0; p < P; ++p) {
+            const f4v v = acc[rb][p] + red[rb * P + p][lane];
             float *dst = a.part + (((size_t)split * a.ptotal + a.pbase + p) * a.nrow_pad +
                                    j0 + rb * 16 + rq) * 16 + c;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) dst[r * 16] = acc[rb][p][r];
+            for (int r = 0; r < 4; ++r) dst[r * 16] = v[r];
         }
 }
 
@@ -248,16 +266,16 @@ hipError_t gram_go(const GramArgs &a, bool vec, unsigned nb, hipStream_t s) {
 void gram_plan(int n, int &nrowblk, int &splits, int &cpw) {
     nrowblk = (n + GR_ROWS - 1) / GR_ROWS;
     const int chunks = (n + GR_CHUNK - 1) / GR_CHUNK;
-    // enough wavefronts to fill the chip, at least 4 column chunks each
-    int want = std::max(1, (2048 + nrowblk - 1) / nrowblk);
-    want = std::min(want, std::max(1, chunks / 4));
+    // enough workgroups to fill the chip, at least 4 column chunks per
+    // wavefront
+    int want = std::max(1, (1024 + nrowblk - 1) / nrowblk);
+    want = std::min(want, std::max(1, chunks / (4 * GR_WAVES)));
     cpw = GR_CHUNK * ((chunks + want - 1) / want);
     splits = (n + cpw - 1) / cpw;
 }
 
 hipError_t launch_gram(const GramArgs &a, int G, bool mean, hipStream_t s) {
-    const long waves = (long)a.nrowblk * a.splits;
-    const unsigned nb = (unsigned)((waves + GR_WAVES - 1) / GR_WAVES);
+    const unsigned nb = (unsigned)((long)a.nrowblk * a.splits);
     bool vec = a.n % 4 == 0;
     for (int i = 0; i < a.nsrc && vec; ++i)
         vec = (reinterpret_cast<uintptr_t>(a.dp.p[i]) & 15) == 0;

@@ -237,8 +237,9 @@ hipError_t launch_nearest(const float *X, int m, int n, int d, const float *dnew
 
 // ---- classical MDS initialisation (cmds.hip) --------------------------
 // (A o A) V for up to GR_MAXP problems of one launch: the mean of all m
-// Delta_i and/or a group of modalities.  Each wavefront takes GR_ROWS rows
-// and the cpw columns of one split; results go to part[split][p][row][16]
+// Delta_i and/or a group of modalities.  Each workgroup takes GR_ROWS rows
+// and the cpw columns of one split (its wavefronts interleaving 32-column
+// steps); results go to part[split][p][row][16]
 // (nrow_pad = nrowblk GR_ROWS rows, 16 columns of which the first K are
 // meaningful), summed over the splits by launch_gram_combine.
 constexpr int GR_RB = 4;                // 16-row MFMA blocks per wavefront
@@ -256,7 +257,7 @@ struct GramArgs {
     int pbase, ptotal;            // first global problem index; problems of the run
     int nrowblk, splits, cpw, nrow_pad;
 };
-// Wavefront grid of an n x n product: row blocks, column splits and
+// Workgroup grid of an n x n product: row blocks, column splits and
 // columns per split (a multiple of GR_CHUNK).
 void gram_plan(int n, int &nrowblk, int &splits, int &cpw);
 // G modalities i0..i0+G-1 (G <= 4) and, with mean, the mean first (then
