@@ -3,6 +3,7 @@
 // the enqueueing of Algorithm 2's loop on the caller's stream.
 #include "fjofc.h"
 #include "fjofc_internal.h"
+#include "tile_spec.h"
 
 #include <cmath>
 #include <cstdarg>
@@ -203,17 +204,16 @@ constexpr int kDefaultVariant = 5;
 // Tile shape of the in-sample stream: th rows x (64 cpl) columns and the
 // kernel variant.  Order of precedence: FJOFC_TILE, the autotuned cache
 // (FJOFC_TUNE_TABLE, else tune_cache.txt next to the library) rows of the
-// device's architecture, the built-in default.
-struct TuneRow {
-    std::string arch;
-    int d, nmax, th, variant;
-};
+// device's architecture, the built-in default.  The parsing and the row
+// choice are in tile_spec.h.
 
 // A tile height is a multiple of the 8-row group of every variant.
 bool valid_th(int th) { return th >= 8 && th <= 2048 && th % 8 == 0; }
+bool valid_tile(int th, int variant) {
+    return valid_th(th) && variant >= 0 && variant < kNumVariants;
+}
 
-// The cache: lines "arch d n_max tile_height variant" ('#' starts a
-// comment), read once per process.
+// The cache, read once per process.
 std::vector<TuneRow> &tune_table() {
     static std::vector<TuneRow> rows;
     static std::once_flag once;
@@ -231,18 +231,10 @@ std::vector<TuneRow> &tune_table() {
             }
         }
         if (FILE *f = path.empty() ? nullptr : std::fopen(path.c_str(), "r")) {
-            char line[256], arch[64];
-            while (std::fgets(line, sizeof line, f)) {
-                TuneRow r;
-                if (line[0] == '#') continue;
-                if (std::sscanf(line, "%63s %d %d %d %d", arch, &r.d, &r.nmax, &r.th,
-                                &r.variant) == 5 &&
-                    r.variant >= 0 && r.variant < kNumVariants && valid_th(r.th) && r.d >= 1 &&
-                    r.nmax >= 2) {
-                    r.arch = arch;
-                    rows.push_back(r);
-                }
-            }
+            char line[256];
+            TuneRow r;
+            while (std::fgets(line, sizeof line, f))
+                if (parse_tune_line(line, valid_tile, r)) rows.push_back(r);
             std::fclose(f);
         }
     });
@@ -269,60 +261,11 @@ std::string device_arch() {
     return a;
 }
 
-// FJOFC_TILE: "th:variant" for every problem, or a comma-separated list of
-// "d:n_lo:n_hi:th:variant" entries, each for the problems of that d with
-// n_lo <= n <= n_hi (the first matching entry applies).  Returns whether
-// it set th and variant.
-bool tile_override(int n, int d, int &th, int &variant) {
-    const char *e = std::getenv("FJOFC_TILE");
-    if (!e || !*e) return false;
-    std::string list(e);
-    size_t pos = 0;
-    while (pos <= list.size()) {
-        const size_t end = std::min(list.find(',', pos), list.size());
-        const std::string it = list.substr(pos, end - pos);
-        pos = end + 1;
-        int f[5];
-        char tail = 0;
-        const int k = std::sscanf(it.c_str(), "%d:%d:%d:%d:%d%c", &f[0], &f[1], &f[2], &f[3],
-                                  &f[4], &tail);
-        if (k == 2 && f[1] >= 0 && f[1] < kNumVariants && valid_th(f[0])) {
-            th = f[0];
-            variant = f[1];
-            return true;
-        }
-        if (k == 5 && f[0] == d && f[1] <= n && n <= f[2] && f[4] >= 0 &&
-            f[4] < kNumVariants && valid_th(f[3])) {
-            th = f[3];
-            variant = f[4];
-            return true;
-        }
-    }
-    return false;
-}
-
 void choose_tiles(int n, int d, int &th, int &variant) {
     th = 256;
     variant = kDefaultVariant;
-    if (!tile_override(n, d, th, variant)) {
-        // the device's rows of d, else those of the nearest tabulated d (the
-        // larger one on a tie): the tile follows n, and a nearby d has a
-        // similar register footprint
-        const std::string arch = device_arch();
-        int dt = -1;
-        for (const TuneRow &r : tune_table()) {
-            if (r.arch != arch) continue;
-            const int e = std::abs(r.d - d), et = std::abs(dt - d);
-            if (dt < 0 || e < et || (e == et && r.d > dt)) dt = r.d;
-        }
-        int best = -1;
-        for (const TuneRow &r : tune_table())
-            if (r.arch == arch && r.d == dt && n <= r.nmax && (best < 0 || r.nmax < best)) {
-                best = r.nmax;
-                th = r.th;
-                variant = r.variant;
-            }
-    }
+    if (!parse_tile_override(std::getenv("FJOFC_TILE"), n, d, valid_tile, th, variant))
+        pick_tune_row(tune_table(), device_arch(), n, d, th, variant);
     // each of the variant's R row slabs holds whole 8-row groups
     const int unit = 8 * kVariants[variant].r;
     th = (th + unit - 1) / unit * unit;

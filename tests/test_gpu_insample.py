@@ -115,11 +115,16 @@ def test_one_transform_parity(ctx, monkeypatch, tile, m, n, d):
     assert rg["stress"] == pytest.approx(s1, rel=2e-5)
 
 
-@pytest.mark.parametrize("m,n,d", [(2, 3600, 3), (2, 7000, 5), (2, 14000, 2)])
-def test_one_transform_parity_table_tiles_mid_sizes(ctx, m, n, d):
-    """One transform at mid-size n with the tiles the tuning table picks
-    there (shared 4 x 1 and 2 x 2 wavefront tiles several hundred rows
-    tall), against the oracle."""
+@pytest.mark.parametrize("m,n,d", [(2, 3600, 3), (2, 7000, 5), (2, 14000, 2), (2, 3000, 4),
+                                   (2, 2500, 8), (1, 4100, 1), (2, 5000, 6), (2, 2200, 7)])
+def test_one_transform_parity_table_tiles_mid_sizes(ctx, monkeypatch, m, n, d):
+    """One transform at mid-size n with the tiles the tile cache picks there
+    (shared 4 x 1 and 2 x 2 wavefront tiles several hundred rows tall; d = 1,
+    4, 6, 7, 8 have no rows of their own and take the nearest d's), against
+    the oracle."""
+    monkeypatch.delenv("FJOFC_TILE", raising=False)
+    th, var = fjofc.fjofc_tile_choice(ctx, n, d)
+    assert th >= 8 and 0 <= var <= 5
     wmat = _general_wmat(m, seed=n)
     delta, _, X0 = _problem(500 + d, m, n, d, wmat=wmat)
     X1o = orc.guttman(delta, wmat, X0)
