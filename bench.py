@@ -26,16 +26,22 @@ if ROOT not in sys.path:
 METRIC = "fJOFC Δ-pairs/s & HBM GB/s; time-to-stress-tol, learned warm start vs plain"
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_insample_stream_m3_n20000_d5.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_1502_03391_amd", "csrc", "insample.hip")
+CSRC = os.path.join(ROOT, "paper_1502_03391_amd", "csrc")
 TILE_CACHE = os.path.join(ROOT, "paper_1502_03391_amd", "tune_cache.txt")
-# the stream kernel and the cache that picks its tile
-STREAM_SRC = (KERNEL_SRC, TILE_CACHE)
+# the stream kernel (its device code and the D = 5..8 instantiations) and
+# the cache that picks its tile
+STREAM_SRC = (os.path.join(CSRC, "stream_dev.h"), os.path.join(CSRC, "stream_hi.hip"),
+              TILE_CACHE)
+KERNEL_SRC = STREAM_SRC[0]
 OOS_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_oos_m2_n10000_d5.json")
 OOS_SRC = os.path.join(ROOT, "paper_1502_03391_amd", "csrc", "oos.hip")
 BATCHED_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_batched_512_uneven.json")
 # the batch's kernels and its launch plan
-BATCHED_SRC = (KERNEL_SRC, os.path.join(ROOT, "paper_1502_03391_amd", "csrc", "host.cpp"),
-               TILE_CACHE)
+# the lockstep batch: stream kernels of every D, the finalize and reduce
+# kernels, the launch plan and the tiles
+BATCHED_SRC = (os.path.join(CSRC, "stream_dev.h"), os.path.join(CSRC, "stream_lo.hip"),
+               os.path.join(CSRC, "stream_hi.hip"), os.path.join(CSRC, "insample.hip"),
+               os.path.join(CSRC, "host.cpp"), TILE_CACHE)
 
 
 def kernel_hash(src=KERNEL_SRC) -> str:

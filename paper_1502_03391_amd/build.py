@@ -19,8 +19,10 @@ LIB = os.path.join(HERE, "libfjofc.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["insample.hip", "oos.hip", "cmds.hip", "mlp.hip", "validate.hip", "host.cpp",
-           "mlp_host.cpp", "init_host.cpp"]
+# longest compiles first: the persistent kernel tiers and the stream halves
+SOURCES = ["batch8.hip", "batch5.hip", "stream_hi.hip", "stream_lo.hip", "insample.hip",
+           "oos.hip", "cmds.hip", "mlp.hip", "validate.hip", "host.cpp", "mlp_host.cpp",
+           "init_host.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -40,7 +42,9 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    if jobs <= 0:
+        jobs = max(1, min(8, os.cpu_count() or 1))
     os.makedirs(BUILD, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))

@@ -113,7 +113,7 @@ inline int commens_blocks(const TriGeom &g, int D) {
     return g.npad / FIN_ROWS * D;
 }
 
-// ---- launchers (insample.hip) ----------------------------------------
+// ---- in-sample launchers (insample.hip; kernels in stream_*.hip) -----
 // Stream kernels for one (D, variant, vec4) group of items; `cur` selects
 // the configuration buffer Xs[cur].
 hipError_t launch_stream(int D, int variant, int vec4, const InstDesc *insts,
@@ -134,7 +134,7 @@ hipError_t launch_copy_out(const InstDesc *insts, int count, hipStream_t s);
 hipError_t launch_to_soa(const TriGeom &g, int D, const float *X, float *Xs,
                          hipStream_t s);
 
-// ---- persistent batched launch (insample.hip) --------------------------
+// ---- persistent batched launch (insample.hip, batch5.hip, batch8.hip) -
 // One launch runs every transform of every problem of a batch.  Workgroups
 // of BATCH_BLOCK threads take tasks from a queue in a fixed order (a task is
 // a group of tiles, of finalize row items or one reduce, of one problem); a
