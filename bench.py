@@ -25,6 +25,12 @@ if ROOT not in sys.path:
 
 METRIC = "fJOFC Δ-pairs/s & HBM GB/s; time-to-stress-tol, learned warm start vs plain"
 PEAK_HBM_GBS = 8000.0
+# VALU issue peak without packed FP32 (disabled in every build): 256 CUs x
+# 4 SIMDs x 16 lanes per clock x 2.4 GHz, in FP32 lane-operations per second
+PEAK_VALU_OPS = 256 * 64 * 2.4e9
+# issue slots one unordered pair needs at d = 5: 5 subtractions, 5 FMAs for
+# d^2, v_rsq (2 slots), a multiply, 10 FMAs for the row and column sums
+SLOTS_PER_PAIR_D5 = 23
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_insample_stream_m3_n20000_d5.json")
 CSRC = os.path.join(ROOT, "paper_1502_03391_amd", "csrc")
 TILE_CACHE = os.path.join(ROOT, "paper_1502_03391_amd", "tune_cache.txt")
@@ -184,6 +190,15 @@ def main():
                      "launches": prof["stream_launches"],
                      "avg_launch_ms": avg_ms,
                      "bytes_per_launch": per_launch_bytes},
+        "roofline_alu": {"bound": "alu", "unit": "lane-op/s",
+                         "achieved": SLOTS_PER_PAIR_D5 * per_launch_bytes / 4.0 / (avg_ms * 1e-3),
+                         "peak": PEAK_VALU_OPS,
+                         "frac": SLOTS_PER_PAIR_D5 * per_launch_bytes / 4.0 / (avg_ms * 1e-3)
+                         / PEAK_VALU_OPS,
+                         "slots_per_pair": SLOTS_PER_PAIR_D5,
+                         "note": "secondary: the stream's issue-slot work per pair against the "
+                                 "non-packed FP32 VALU peak at 2.4 GHz (d = 5 only)"}
+        if d == 5 else None,
         "kernel_ms_per_step": {k: prof[k] / args.steps for k in
                                ("stream_ms", "edge_ms", "finalize_ms", "reduce_ms")},
         "final_stress_norm": res["stress_norm"],
