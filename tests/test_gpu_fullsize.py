@@ -75,6 +75,41 @@ def test_insample_full_size_transform_and_history(ctx):
     assert np.all(np.diff(h) <= 1e-6 * h[:-1])
 
 
+def test_insample_beyond_32_bit_indices(ctx):
+    """m = 1, n = 47000: n^2 = 2.2e9 entries (8.8 GB of Delta) exceed 2^31,
+    so every offset into Delta must be 64-bit.  The validation pass finds
+    no offending entry, and after one entry beyond index 2^31 is made
+    negative it reports exactly that entry; one transform from a seeded
+    start against the oracle element by element, and the stresses of X_0
+    and X_1."""
+    n, d = 47000, 2
+    assert n * n > 2 ** 31
+    views, _, X0 = gen.latent_views(4700, n, 1, 4, 0.2, d)
+    dev = torch.device("cuda:0")
+    delta = [gen.pairwise_dist_torch(views[0], dev)]
+    assert fjofc.fjofc_validate_delta(ctx, delta[0]) == -1
+    wmat = gen.uniform_wmat(1, 0.5)
+    X0f = X0.astype(np.float32)
+    X = _f32(X0f)
+    res, hist = fjofc.fjofc_embed(ctx, delta, wmat, X, 1, want_hist=True)
+    torch.cuda.synchronize()
+    Xg = X.cpu().numpy().astype(np.float64)
+    host = delta[0].cpu().numpy()
+    j, l = 46000, 46999
+    assert j * n + l > 2 ** 31
+    delta[0][j, l] = -1.0
+    with pytest.raises(fjofc.FjofcError) as e:
+        fjofc.fjofc_validate_delta(ctx, delta[0])
+    assert e.value.where == j * n + l
+    del delta
+    torch.cuda.empty_cache()
+    X0c = X0f.astype(np.float64)
+    X1o = orc.guttman([host], wmat, X0c)
+    np.testing.assert_allclose(Xg, X1o, rtol=0, atol=2e-5 * np.abs(X1o).max())
+    assert hist[0] == pytest.approx(orc.stress([host], wmat, X0c)[0], rel=2e-6)
+    assert res["stress"] == pytest.approx(orc.stress([host], wmat, X1o)[0], rel=2e-5)
+
+
 def test_oos_full_launch_sampled_objects(ctx):
     """n=10000, m=2, d=5, one launch of 4096 objects, 100 transforms:
     sampled objects against the oracle run on those objects alone."""
