@@ -50,8 +50,10 @@
  *  - FJOFC_OOS_OB      1..4 objects per out-of-sample workgroup (default 4);
  *  - FJOFC_OOS_SCALAR  any value: the out-of-sample stream uses 4-byte
  *                      loads even when n % 4 == 0;
- *  - FJOFC_GEMM_WAVES  "1" or "4": wavefronts per workgroup of the network's
- *                      matrix products (default: by product size).
+ *  - FJOFC_GEMM_WAVES  the form of the network's matrix products: "1" one
+ *                      wavefront per 32 x 32 tile, "4" 2 x 2 wavefronts per
+ *                      64 x 64 tile, "k" four wavefronts splitting K per
+ *                      32 x 32 tile (default: by product size).
  * Debug switch:
  *  - FJOFC_VALIDATE    any value but "0": every in-sample call (fjofc_embed*,
  *                      fjofc_stress, fjofc_batch_create) first runs

@@ -72,6 +72,59 @@ __device__ __forceinline__ bf8 load_frag(const uint16_t *__restrict__ p, long ld
     return f.v;
 }
 
+// The epilogue of a wavefront's 32 x 32 outputs (acc[i][j] holds rows
+// m0 + 16 i + 4 (lane / 16) + v, column n0 + 16 j + lane % 16).
+template <int EPI>
+__device__ __forceinline__ void gemm_store(const f4 (&acc)[2][2], int M, int N, int m0, int n0,
+                                           int lane, const GemmEpi &e) {
+    const int li = lane & 15;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int col = n0 + 16 * j + li;
+            const int rb = m0 + 16 * i + 4 * (lane >> 4);
+            if (col >= N) continue;
+            uint16_t hb[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = rb + v;
+                hb[v] = 0;
+                if (row >= M) continue;
+                const long o = (long)row * e.ldc + col;
+                const float x = acc[i][j][v];
+                if (EPI == GEMM_HIDDEN) {
+                    const float z = x + e.bias[col];
+                    e.outf[o] = z;
+                    hb[v] = f2bf(gelu(z));
+                    e.outb[o] = hb[v];
+                } else if (EPI == GEMM_LAST) {
+                    e.outf[o] = x + e.bias[col];
+                } else if (EPI == GEMM_BWD) {
+                    const float g = x * gelu_grad(e.Z[o]);
+                    e.outf[o] = g;
+                    hb[v] = f2bf(g);
+                    e.outb[o] = hb[v];
+                } else {
+                    e.outf[o] = x;
+                }
+            }
+            if ((EPI == GEMM_HIDDEN || EPI == GEMM_BWD) && e.outbT) {
+                uint16_t *t = e.outbT + (long)col * e.ldt + rb;
+                if (rb + 4 <= M && (e.ldt & 3) == 0) {
+                    uint2 w;
+                    w.x = (uint32_t)hb[0] | ((uint32_t)hb[1] << 16);
+                    w.y = (uint32_t)hb[2] | ((uint32_t)hb[3] << 16);
+                    *reinterpret_cast<uint2 *>(t) = w;
+                } else {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        if (rb + v < M) t[v] = hb[v];
+                }
+            }
+        }
+}
+
 // WM x WN wavefronts per workgroup (a 32 WM x 32 WN output tile).
 template <int EPI, bool VEC, int WM, int WN>
 __global__ __launch_bounds__(WAVE *WM *WN) void gemm_kernel(int M, int N, int K,
@@ -119,51 +172,78 @@ __global__ __launch_bounds__(WAVE *WM *WN) void gemm_kernel(int M, int N, int K,
                                                                         0, 0, 0);
         }
     }
+    gemm_store<EPI>(acc, M, N, m0, n0, lane, e);
+}
+
+// Split K: a workgroup of GSK wavefronts per 32 x 32 output tile, wavefront
+// w multiplying the w-th quarter of K (in GK steps, all of its loads issued
+// ahead through the same register ring), the partial tiles then added
+// through LDS in a fixed order (0 + (1 + (2 + 3))) before wavefront 0's
+// epilogue.  Small products (few output tiles, K of a few hundred) are
+// otherwise a chain of dependent K steps on too few wavefronts.
+constexpr int GSK = 4;
+template <int EPI, bool VEC>
+__global__ __launch_bounds__(WAVE *GSK) void gemm_sk_kernel(int M, int N, int K,
+                                                           const uint16_t *__restrict__ A,
+                                                           long lda,
+                                                           const uint16_t *__restrict__ Bt,
+                                                           long ldb, GemmEpi e) {
+    __shared__ f4 red[GSK - 1][4][WAVE];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int m0 = blockIdx.y * 32, n0 = blockIdx.x * 32;
+    const int li = lane & 15, lk = (lane >> 4) * 8;
+    const int steps = (K + GK - 1) / GK;
+    const int per = (steps + GSK - 1) / GSK;
+    const int kb = wv * per * GK, ke = min(K, kb + per * GK);
+    f4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int col = n0 + 16 * j + li;
-            const int rb = m0 + 16 * i + 4 * (lane >> 4);
-            if (col >= N) continue;
-            uint16_t hb[4];
+        for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    bf8 a[GNB][2], b[GNB][2];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = rb + v;
-                hb[v] = 0;
-                if (row >= M) continue;
-                const long o = (long)row * e.ldc + col;
-                const float x = acc[i][j][v];
-                if (EPI == GEMM_HIDDEN) {
-                    const float z = x + e.bias[col];
-                    e.outf[o] = z;
-                    hb[v] = f2bf(gelu(z));
-                    e.outb[o] = hb[v];
-                } else if (EPI == GEMM_LAST) {
-                    e.outf[o] = x + e.bias[col];
-                } else if (EPI == GEMM_BWD) {
-                    const float g = x * gelu_grad(e.Z[o]);
-                    e.outf[o] = g;
-                    hb[v] = f2bf(g);
-                    e.outb[o] = hb[v];
-                } else {
-                    e.outf[o] = x;
-                }
-            }
-            if ((EPI == GEMM_HIDDEN || EPI == GEMM_BWD) && e.outbT) {
-                uint16_t *t = e.outbT + (long)col * e.ldt + rb;
-                if (rb + 4 <= M && (e.ldt & 3) == 0) {
-                    uint2 w;
-                    w.x = (uint32_t)hb[0] | ((uint32_t)hb[1] << 16);
-                    w.y = (uint32_t)hb[2] | ((uint32_t)hb[3] << 16);
-                    *reinterpret_cast<uint2 *>(t) = w;
-                } else {
+    for (int st = 0; st < GNB - 1; ++st)
 #pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        if (rb + v < M) t[v] = hb[v];
-                }
-            }
+        for (int i = 0; i < 2; ++i) {
+            a[st][i] = load_frag<VEC>(A, lda, m0 + 16 * i + li, M, kb + st * GK + lk, ke);
+            b[st][i] = load_frag<VEC>(Bt, ldb, n0 + 16 * i + li, N, kb + st * GK + lk, ke);
         }
+    for (int k0 = kb; k0 < ke; k0 += GNB * GK) {
+#pragma unroll
+        for (int u = 0; u < GNB; ++u) {
+            const int kk = k0 + u * GK;
+            if (kk >= ke) break;
+            const int kn = kk + (GNB - 1) * GK, un = (u + GNB - 1) % GNB;
+            if (kn < ke) {
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    a[un][i] = load_frag<VEC>(A, lda, m0 + 16 * i + li, M, kn + lk, ke);
+                    b[un][i] = load_frag<VEC>(Bt, ldb, n0 + 16 * i + li, N, kn + lk, ke);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u][i], b[u][j], acc[i][j],
+                                                                        0, 0, 0);
+        }
+    }
+    if (wv > 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) red[wv - 1][q][lane] = acc[q >> 1][q & 1];
+    }
+    __syncthreads();
+    if (wv != 0) return;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        f4 t = red[GSK - 2][q][lane];
+#pragma unroll
+        for (int w = GSK - 3; w >= 0; --w) t = red[w][q][lane] + t;
+        acc[q >> 1][q & 1] += t;
+    }
+    gemm_store<EPI>(acc, M, N, m0, n0, lane, e);
 }
 
 // out (C x R) = transpose of in (R x C), BF16, through a 32 x 33 LDS tile.
@@ -403,31 +483,49 @@ static hipError_t gemm_epi(bool vec, int M, int N, int K, const uint16_t *A, lon
 }
 
 template <int EPI>
-static hipError_t gemm_waves(bool wide, bool vec, int M, int N, int K, const uint16_t *A,
+static hipError_t gemm_sk(bool vec, int M, int N, int K, const uint16_t *A, long lda,
+                          const uint16_t *Bt, long ldb, const GemmEpi &e, hipStream_t s) {
+    const dim3 grid((unsigned)((N + 31) / 32), (unsigned)((M + 31) / 32));
+    if (vec)
+        gemm_sk_kernel<EPI, true><<<grid, WAVE * GSK, 0, s>>>(M, N, K, A, lda, Bt, ldb, e);
+    else
+        gemm_sk_kernel<EPI, false><<<grid, WAVE * GSK, 0, s>>>(M, N, K, A, lda, Bt, ldb, e);
+    return hipGetLastError();
+}
+
+enum { GEMM_FORM_ONE = 0, GEMM_FORM_WIDE = 1, GEMM_FORM_SPLITK = 2 };
+
+template <int EPI>
+static hipError_t gemm_waves(int form, bool vec, int M, int N, int K, const uint16_t *A,
                              long lda, const uint16_t *Bt, long ldb, const GemmEpi &e,
                              hipStream_t s) {
-    return wide ? gemm_epi<EPI, 2, 2>(vec, M, N, K, A, lda, Bt, ldb, e, s)
-                : gemm_epi<EPI, 1, 1>(vec, M, N, K, A, lda, Bt, ldb, e, s);
+    if (form == GEMM_FORM_WIDE) return gemm_epi<EPI, 2, 2>(vec, M, N, K, A, lda, Bt, ldb, e, s);
+    if (form == GEMM_FORM_SPLITK) return gemm_sk<EPI>(vec, M, N, K, A, lda, Bt, ldb, e, s);
+    return gemm_epi<EPI, 1, 1>(vec, M, N, K, A, lda, Bt, ldb, e, s);
 }
 
 // Workgroups of 2 x 2 wavefronts (64 x 64 outputs) when that already gives
-// at least two workgroups per CU; otherwise one wavefront per 32 x 32
-// tile, so that the same wavefronts spread over all CUs.  FJOFC_GEMM_WAVES
-// ("1" or "4") forces one of the two.
+// at least two workgroups per CU.  Otherwise each 32 x 32 tile gets a
+// workgroup of four wavefronts splitting K (K of at least four steps), or
+// one wavefront.  FJOFC_GEMM_WAVES ("1", "4" or "k") forces one of the
+// three.
 constexpr long GEMM_WIDE_MIN_TILES = 512;
 
-bool gemm_wide(int M, int N) {
+int gemm_form(int M, int N, int K) {
     if (const char *v = std::getenv("FJOFC_GEMM_WAVES")) {
-        if (v[0] == '1') return false;
-        if (v[0] == '4') return true;
+        if (v[0] == '1') return GEMM_FORM_ONE;
+        if (v[0] == '4') return GEMM_FORM_WIDE;
+        if (v[0] == 'k') return GEMM_FORM_SPLITK;
     }
-    return (long)((M + GB - 1) / GB) * ((N + GB - 1) / GB) >= GEMM_WIDE_MIN_TILES;
+    if ((long)((M + GB - 1) / GB) * ((N + GB - 1) / GB) >= GEMM_WIDE_MIN_TILES)
+        return GEMM_FORM_WIDE;
+    return K >= GSK * GK ? GEMM_FORM_SPLITK : GEMM_FORM_ONE;
 }
 
 hipError_t launch_gemm(int epi, int M, int N, int K, const uint16_t *A, long lda,
                        const uint16_t *Bt, long ldb, const GemmEpi &e, hipStream_t s) {
     if (M <= 0 || N <= 0) return hipSuccess;
-    const bool wide = gemm_wide(M, N);
+    const int wide = gemm_form(M, N, K);
     const bool vec = (lda % 8 == 0) && (ldb % 8 == 0) &&
                      ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(Bt)) & 15) == 0;
     switch (epi) {

@@ -68,13 +68,14 @@ def _net(ctx, dims, B, seed):
     return net, params, x, y, xb
 
 
-@pytest.mark.parametrize("waves", [None, "1", "4"])
+@pytest.mark.parametrize("waves", [None, "1", "4", "k"])
 @pytest.mark.parametrize("dims,B", [([64, 48, 40, 5], 37), ([512, 512, 512, 512, 5], 1024),
                                     ([100, 70, 3], 130), ([16, 16], 1)])
 def test_forward_and_gradients(ctx, monkeypatch, dims, B, waves):
     """Forward output, loss and every gradient against the FP64 oracle at
     the same BF16 rounding points, with the matrix products' workgroups
-    chosen by size or forced to one or to 2 x 2 wavefronts."""
+    chosen by size or forced to one wavefront, to 2 x 2 wavefronts, or to
+    four wavefronts splitting K (also where K has fewer than four steps)."""
     if waves:
         monkeypatch.setenv("FJOFC_GEMM_WAVES", waves)
     net, params, x, y, xb = _net(ctx, dims, B, 7 + B)
