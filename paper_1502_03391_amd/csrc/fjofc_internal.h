@@ -203,10 +203,13 @@ hipError_t launch_batch_persistent(const BatchArgs &a, int maxd, int maxm, int g
 int batch_resident_blocks(int maxd, int maxm, size_t lds);
 // Tiles per stream task: one-wavefront tiles, eight per wavefront; shared
 // tiles, eight in turn.  Finalize row items per task.  Every task ends in
-// an agent-scope release (an L2 write-back) and starts after an acquire,
-// so tasks are made coarse; a sweep of the uneven 512-problem batch
-// measured (32, 8, 16) at 0.236 s against 0.300 s for (16, 4, 4), 0.249 s
-// for (32, 8, 8), 0.253 s for (32, 8, 32) and 0.292 s for (64, 16, 16).
+// an agent-scope release and starts after an acquire, and a task that must
+// wait holds its workgroup, so tasks are made coarse, but not so coarse
+// that the last ones of a transform run alone.  On the uneven 512-problem
+// batch with 256 x 512 tiles for every problem, a sweep of 12 settings
+// ranked (32, 8, 16) first (0.236 s; (32, 8, 8) 0.249 s, (32, 8, 32)
+// 0.253 s, (64, 16, 16) 0.292 s); with the tile cache's tiles it takes
+// 0.289 s against 0.300 s for (16, 4, 4).
 constexpr int BATCH_TILES_1W = 32, BATCH_TILES_SHARED = 8, BATCH_ROWS = 16;
 // Dynamic LDS one persistent workgroup needs for a problem's stream tasks.
 size_t batch_stream_lds(int D, int variant, size_t tile_lds);
