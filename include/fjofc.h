@@ -361,6 +361,18 @@ int fjofc_mlp_get_grads(fjofc_mlp *net, float *const *dW, float *const *db,
 /* One Adam step with the stored gradients (FP32 masters, BF16 refreshed). */
 int fjofc_mlp_adam(fjofc_mlp *net, float lr, float beta1, float beta2,
                    float eps, void *stream);
+/* `steps` training steps in one call: step q runs fjofc_mlp_backward on rows
+ * [q B, (q + 1) B) of x (N x dims[0] BF16) and y (N x dims[L] FP32), then
+ * fjofc_mlp_adam with learning rate lr[q] (host array of `steps` values)
+ * and beta1, beta2, eps.  The same kernels in the same order as those calls,
+ * so the parameters come out bitwise the same; each step's MSE is added to
+ * *loss_sum (device FP64, optional).  FJOFC_EINVAL if steps B > N, B is
+ * outside [1, max_batch], a learning rate is negative or NaN, or the Adam
+ * constants are out of range.  Lets a training loop run without a host
+ * call per step.                                                           */
+int fjofc_mlp_train_steps(fjofc_mlp *net, const unsigned short *x, const float *y,
+                          int N, int B, int steps, const float *lr, float beta1,
+                          float beta2, float eps, double *loss_sum, void *stream);
 /* Features of k new objects: x[o][i*L + l] = BF16((delta_new[o][i][lm[l]]
  * - mu[i*L + l]) * inv_sd[i*L + l]); delta_new is k x m x n FP32 (as for
  * fjofc_oos), landmarks L int32 indices in [0, n) (clamped).              */

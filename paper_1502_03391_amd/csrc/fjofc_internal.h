@@ -317,9 +317,10 @@ hipError_t launch_gemm(int epi, int M, int N, int K, const uint16_t *A, long lda
 hipError_t launch_transpose16(const uint16_t *in, long ld_in, int R, int C, uint16_t *out,
                               long ld_out, hipStream_t s);
 // GbT (optional): the BF16 gradient transposed (k x B, leading dimension ldt).
-// scratch: at least 64 doubles.
+// scratch: at least 64 doubles.  accumulate: *loss += the MSE instead of =.
 hipError_t launch_mse(const float *out, const float *y, int B, int k, float *G, uint16_t *Gb,
-                      uint16_t *GbT, long ldt, double *loss, double *scratch, hipStream_t s);
+                      uint16_t *GbT, long ldt, double *loss, double *scratch, hipStream_t s,
+                      bool accumulate = false);
 // scratch: at least 16 N doubles.
 hipError_t launch_colsum(const float *G, int B, int N, float *db, double *scratch,
                          hipStream_t s);

@@ -298,10 +298,10 @@ __global__ __launch_bounds__(256) void mse_kernel(const float *__restrict__ out,
 
 // loss = (sum of the MSE_BLOCKS parts, in order) / (B k).
 __global__ void mse_finish_kernel(const double *__restrict__ part, long tot,
-                                  double *__restrict__ loss) {
+                                  double *__restrict__ loss, int accumulate) {
     double s = 0.0;
     for (int q = 0; q < MSE_BLOCKS; ++q) s += part[q];
-    loss[0] = s / (double)tot;
+    loss[0] = accumulate ? loss[0] + s / (double)tot : s / (double)tot;
 }
 
 // Bias gradient: column sums of G (B x N), two passes.  Pass 1: workgroup
@@ -545,11 +545,12 @@ hipError_t launch_transpose16(const uint16_t *in, long ld_in, int R, int C, uint
 }
 
 hipError_t launch_mse(const float *out, const float *y, int B, int k, float *G, uint16_t *Gb,
-                      uint16_t *GbT, long ldt, double *loss, double *scratch, hipStream_t s) {
+                      uint16_t *GbT, long ldt, double *loss, double *scratch, hipStream_t s,
+                      bool accumulate) {
     mse_kernel<<<MSE_BLOCKS, 256, 0, s>>>(out, y, B, k, G, Gb, GbT, ldt, scratch);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !loss) return e;
-    mse_finish_kernel<<<1, 1, 0, s>>>(scratch, (long)B * k, loss);
+    mse_finish_kernel<<<1, 1, 0, s>>>(scratch, (long)B * k, loss, accumulate ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -258,20 +258,18 @@ int fjofc_mlp_predict_start(fjofc_mlp *n, const unsigned short *x, int B, int m,
     return FJOFC_OK;
 }
 
-int fjofc_mlp_backward(fjofc_mlp *n, const unsigned short *x, const float *y, int B, double *loss,
-                       void *stream) {
-    int rc = check_batch(n, B);
-    if (rc) return rc;
-    if (!x || !y) return set_error(FJOFC_EINVAL, "NULL argument");
-    Dev dg(n->device);
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    rc = forward(n, x, B, s);
+namespace {
+
+// Forward, MSE (written to *loss, or added to it with accumulate), backward.
+int backward(fjofc_mlp *n, const unsigned short *x, const float *y, int B, double *loss,
+             bool accumulate, hipStream_t s) {
+    int rc = forward(n, x, B, s);
     if (rc) return rc;
     const int L = n->L;
     int cur = 0;
     HIP_CHECK(launch_transpose16(x, n->dims[0], B, n->dims[0], n->HT[0], n->ldt, s));
     HIP_CHECK(launch_mse(n->out, y, B, n->dims[L], n->Gf[cur], n->Gb[cur], n->GbT[cur], n->ldt,
-                         loss, n->scratch, s));
+                         loss, n->scratch, s, accumulate));
     for (int l = L - 1; l >= 0; --l) {
         const int in = n->dims[l], o = n->dims[l + 1];
         // dW_l = h^T g   (in x o), K = B: both operands feature-major
@@ -297,6 +295,57 @@ int fjofc_mlp_backward(fjofc_mlp *n, const unsigned short *x, const float *y, in
     return FJOFC_OK;
 }
 
+bool adam_args_ok(float lr, float beta1, float beta2, float eps) {
+    return lr >= 0.f && beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps > 0.f;
+}
+
+int adam(fjofc_mlp *n, float lr, float beta1, float beta2, float eps, hipStream_t s) {
+    n->step += 1;
+    const float c1 = (float)(1.0 - std::pow((double)beta1, n->step));
+    const float c2 = (float)(1.0 - std::pow((double)beta2, n->step));
+    HIP_CHECK(launch_adam(n->P, n->G, n->M1, n->M2, n->P16, (long)n->nparam, lr, beta1, beta2, eps,
+                          c1, c2, s));
+    return refresh_wt(n, s);
+}
+
+}  // namespace
+
+int fjofc_mlp_backward(fjofc_mlp *n, const unsigned short *x, const float *y, int B, double *loss,
+                       void *stream) {
+    int rc = check_batch(n, B);
+    if (rc) return rc;
+    if (!x || !y) return set_error(FJOFC_EINVAL, "NULL argument");
+    Dev dg(n->device);
+    return backward(n, x, y, B, loss, false, static_cast<hipStream_t>(stream));
+}
+
+int fjofc_mlp_train_steps(fjofc_mlp *n, const unsigned short *x, const float *y, int N, int B,
+                          int steps, const float *lr, float beta1, float beta2, float eps,
+                          double *loss_sum, void *stream) {
+    int rc = check_batch(n, B);
+    if (rc) return rc;
+    if (steps < 0 || N < 0 || (long long)steps * B > N)
+        return set_error(FJOFC_EINVAL, "%d steps of %d rows need more than N = %d rows", steps, B,
+                         N);
+    if (steps == 0) return FJOFC_OK;
+    if (!x || !y || !lr) return set_error(FJOFC_EINVAL, "NULL argument");
+    if (!adam_args_ok(0.f, beta1, beta2, eps))
+        return set_error(FJOFC_EINVAL, "bad Adam hyper-parameters");
+    for (int q = 0; q < steps; ++q)
+        if (!(lr[q] >= 0.f)) return set_error(FJOFC_EINVAL, "lr[%d] is not >= 0", q);
+    Dev dg(n->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int L = n->L;
+    for (int q = 0; q < steps; ++q) {
+        rc = backward(n, x + (size_t)q * B * n->dims[0], y + (size_t)q * B * n->dims[L], B,
+                      loss_sum, true, s);
+        if (rc) return rc;
+        rc = adam(n, lr[q], beta1, beta2, eps, s);
+        if (rc) return rc;
+    }
+    return FJOFC_OK;
+}
+
 int fjofc_mlp_get_grads(fjofc_mlp *n, float *const *dW, float *const *db, void *stream) {
     if (!n || !dW || !db) return set_error(FJOFC_EINVAL, "NULL argument");
     Dev dg(n->device);
@@ -312,17 +361,10 @@ int fjofc_mlp_get_grads(fjofc_mlp *n, float *const *dW, float *const *db, void *
 
 int fjofc_mlp_adam(fjofc_mlp *n, float lr, float beta1, float beta2, float eps, void *stream) {
     if (!n) return set_error(FJOFC_EINVAL, "mlp is NULL");
-    if (!(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) ||
-        !(eps > 0.f))
+    if (!adam_args_ok(lr, beta1, beta2, eps))
         return set_error(FJOFC_EINVAL, "bad Adam hyper-parameters");
     Dev dg(n->device);
-    n->step += 1;
-    const float c1 = (float)(1.0 - std::pow((double)beta1, n->step));
-    const float c2 = (float)(1.0 - std::pow((double)beta2, n->step));
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    HIP_CHECK(launch_adam(n->P, n->G, n->M1, n->M2, n->P16, (long)n->nparam, lr, beta1, beta2, eps,
-                          c1, c2, s));
-    return refresh_wt(n, s);
+    return adam(n, lr, beta1, beta2, eps, static_cast<hipStream_t>(stream));
 }
 
 int fjofc_mlp_features(fjofc_ctx *ctx, const float *delta_new, int k, int m, int n,

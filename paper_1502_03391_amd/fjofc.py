@@ -29,7 +29,7 @@ EXPORTS = ["fjofc_create", "fjofc_destroy", "fjofc_last_error", "fjofc_strerror"
            "fjofc_embed_batched",
            "fjofc_mlp_create", "fjofc_mlp_destroy", "fjofc_mlp_set_params",
            "fjofc_mlp_get_params", "fjofc_mlp_forward", "fjofc_mlp_backward",
-           "fjofc_mlp_get_grads", "fjofc_mlp_adam", "fjofc_mlp_features",
+           "fjofc_mlp_get_grads", "fjofc_mlp_adam", "fjofc_mlp_train_steps", "fjofc_mlp_features",
            "fjofc_mlp_predict_start", "fjofc_oos_nearest_start", "fjofc_embed_relaxed",
            "fjofc_init_cmds", "fjofc_mlp_loss", "fjofc_mlp_feature_stats",
            "fjofc_oos_consensus", "fjofc_validate_delta", "fjofc_oos_noalloc"]
@@ -127,6 +127,8 @@ def lib():
         L.fjofc_oos_nearest_start.argtypes = [vp, vp, ip, ip, ip, vp, ip, vp, vp]
         L.fjofc_mlp_get_grads.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), vp]
         L.fjofc_mlp_adam.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float, vp]
+        L.fjofc_mlp_train_steps.argtypes = [vp, vp, vp, ip, ip, ip, C.POINTER(C.c_float),
+                                            C.c_float, C.c_float, C.c_float, vp, vp]
         L.fjofc_mlp_features.argtypes = [vp, vp, ip, ip, ip, vp, ip, vp, vp, vp, vp]
         L.fjofc_mlp_loss.argtypes = [vp, vp, vp, ip, vp, vp]
         L.fjofc_mlp_feature_stats.argtypes = [vp, vp, ip, ip, dp, vp, vp, vp]
@@ -468,6 +470,22 @@ class Mlp:
                                     _dev_ptr(y, torch.float32, "y"), int(x.shape[0]),
                                     _dev_ptr(loss, torch.float64, "loss"), _stream_ptr(stream)))
         return loss
+
+    def train_steps(self, x, y, batch, lrs, loss_sum=None, beta1=0.9, beta2=0.999, eps=1e-8,
+                    stream=None):
+        """len(lrs) training steps on consecutive batches of `batch` rows of
+        x (BF16) and y (FP32); each step's MSE is added to loss_sum (device
+        FP64, optional)."""
+        import torch
+        if (x.dim() != 2 or y.dim() != 2 or x.shape[0] != y.shape[0]
+                or x.shape[1] != self.dims[0] or y.shape[1] != self.dims[-1]):
+            raise ValueError("x and y must be N x dims[0] and N x dims[-1]")
+        lr = (C.c_float * len(lrs))(*[float(v) for v in lrs])
+        lp = _dev_ptr(loss_sum, torch.float64, "loss_sum") if loss_sum is not None else None
+        _check(lib().fjofc_mlp_train_steps(self._h, _dev_ptr(x, torch.bfloat16, "x"),
+                                           _dev_ptr(y, torch.float32, "y"), int(x.shape[0]),
+                                           int(batch), len(lrs), lr, float(beta1), float(beta2),
+                                           float(eps), lp, _stream_ptr(stream)))
 
     def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
         _check(lib().fjofc_mlp_adam(self._h, float(lr), float(beta1), float(beta2), float(eps),

@@ -177,20 +177,18 @@ def train_network(ctx, raw, tgt, cfg: WarmStartConfig, log=print):
     ntr = tr_idx.shape[0]
     steps_per_epoch = ntr // cfg.batch
     total = steps_per_epoch * cfg.epochs
-    loss = torch.zeros(1, dtype=torch.float64, device=raw.device)
     hist = []
     step = 0
     for ep in range(cfg.epochs):
         order = tr_idx[torch.from_numpy(rng.permutation(ntr)).to(raw.device)]
         xe, ye = xs[order], tgt[order]
         acc = torch.zeros(1, dtype=torch.float64, device=raw.device)
-        for s in range(steps_per_epoch):
-            sl = slice(s * cfg.batch, (s + 1) * cfg.batch)
-            net.backward(xe[sl], ye[sl], loss)
-            lr = cfg.lr * 0.5 * (1.0 + math.cos(math.pi * step / max(1, total)))
-            net.adam(lr)
-            acc += loss
-            step += 1
+        # one library call per epoch: consecutive batches of the shuffled
+        # rows, each with its cosine learning rate
+        lrs = [cfg.lr * 0.5 * (1.0 + math.cos(math.pi * (step + s) / max(1, total)))
+               for s in range(steps_per_epoch)]
+        net.train_steps(xe, ye, cfg.batch, lrs, acc)
+        step += steps_per_epoch
         vl = evaluate_loss(net, xs[val_idx], tgt[val_idx], cfg.batch)
         hist.append({"epoch": ep, "train_mse": float(acc.item() / steps_per_epoch), "val_mse": vl})
         log(f"[warmstart] epoch {ep}: train {hist[-1]['train_mse']:.4e} val {vl:.4e}")

@@ -168,6 +168,60 @@ def test_training_reduces_loss(ctx):
     assert loss.item() < 0.2 * first
 
 
+@pytest.mark.parametrize("dims,B,steps,N", [([40, 32, 4], 64, 5, 330),
+                                             ([512, 512, 512, 5], 1024, 3, 3 * 1024)])
+def test_train_steps_equals_step_loop(ctx, dims, B, steps, N):
+    """fjofc_mlp_train_steps against the same steps called one by one
+    (backward on consecutive batches, Adam with each step's rate): the
+    parameters, the Adam state's effect on a further step, and the summed
+    loss are bitwise equal; rows beyond steps x B are not read."""
+    rng = np.random.default_rng(B + steps)
+    x = torch.from_numpy(rng.standard_normal((N, dims[0])).astype(np.float32)).cuda()
+    x = x.to(torch.bfloat16)
+    y = torch.from_numpy(rng.standard_normal((N, dims[-1])).astype(np.float32)).cuda()
+    lrs = [1e-3 * (1 + 0.5 * np.cos(q)) for q in range(steps)]
+    a, _, _, _, _ = _net(ctx, dims, B, 21)
+    b, _, _, _, _ = _net(ctx, dims, B, 21)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    acc = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for q in range(steps):
+        a.backward(x[q * B:(q + 1) * B], y[q * B:(q + 1) * B], loss)
+        a.adam(lrs[q])
+        acc += loss
+    tot = torch.zeros(1, dtype=torch.float64, device="cuda")
+    b.train_steps(x, y, B, lrs, tot)
+    # one more step each, so that the first and second moments must agree too
+    a.backward(x[:B], y[:B])
+    a.adam(2e-3)
+    b.train_steps(x[:B], y[:B], B, [2e-3])
+    Wa, ba = a.get_params()
+    Wb, bb = b.get_params()
+    torch.cuda.synchronize()
+    assert tot.item() == acc.item()
+    for l in range(len(Wa)):
+        assert torch.equal(Wa[l], Wb[l]), f"W[{l}]"
+        assert torch.equal(ba[l], bb[l]), f"b[{l}]"
+
+
+def test_train_steps_rejects_bad_arguments(ctx):
+    dims, B = [16, 8, 2], 10
+    net, _, _, _, _ = _net(ctx, dims, B, 2)
+    x = torch.zeros((25, 16), dtype=torch.bfloat16, device="cuda")
+    y = torch.zeros((25, 2), dtype=torch.float32, device="cuda")
+    W0, _ = net.get_params()
+    for lrs in ([1e-3] * 3, [1e-3, -1e-3], [float("nan")]):
+        with pytest.raises(fjofc.FjofcError):
+            net.train_steps(x, y, B, lrs)
+    with pytest.raises(fjofc.FjofcError):
+        net.train_steps(x, y, B, [1e-3], beta1=1.0)
+    with pytest.raises(fjofc.FjofcError):
+        net.train_steps(x, y, B + 1, [1e-3])
+    net.train_steps(x, y, B, [])
+    W1, _ = net.get_params()
+    for a, b in zip(W0, W1):
+        assert torch.equal(a, b)
+
+
 def test_features_kernel(ctx):
     k, m, n, L = 37, 2, 300, 17
     rng = np.random.default_rng(9)
