@@ -119,8 +119,10 @@ inline int commens_blocks(const TriGeom &g, int D) {
 hipError_t launch_stream(int D, int variant, int vec4, const InstDesc *insts,
                          const StreamItem *items, int nitems, int cur,
                          bool stress, bool acc, size_t lds, hipStream_t s);
+// one_thread: one thread per (row, component) forms the slice sums in turn
+// (same bits as one thread per slice; fewer, fuller workgroups).
 hipError_t launch_finalize(int maxm, const InstDesc *insts, const RowItem *rows,
-                           int nrows, int cur, bool want_com, hipStream_t s);
+                           int nrows, int cur, bool want_com, bool one_thread, hipStream_t s);
 hipError_t launch_com(const InstDesc *insts, const RowItem *rows, int nrows,
                       hipStream_t s);
 // One workgroup per instance [0, count).

@@ -536,6 +536,12 @@ struct Fork {
 // flag of the chunk before, so at most one chunk is enqueued past a stop.
 constexpr int kChunk = 32;
 
+// Finalize launches: a launch of many row items (or one beside other groups'
+// streams) takes one thread per row; one of few items (a single large
+// problem) takes one thread per slice, which keeps more loads in flight.
+// Both give the same bits.
+constexpr int kFinOneThreadItems = 2048;
+
 // Called after the transforms [0, p) are enqueued (p a multiple of kChunk,
 // p < iters); sets `stop` when no more transforms need enqueueing.
 using ChunkHook = std::function<int(int p, bool &stop)>;
@@ -567,7 +573,8 @@ int enqueue_loop(fjofc_ctx *ctx, const InstDesc *insts, int count, int maxm,
                                   stress, acc, gr.lds, gs));
             if (fin_com >= 0) {
                 Timed tf(ctx, K_FIN, 0.0, gs);
-                HIP_TRY(launch_finalize(gr.maxm, insts, gr.rows, gr.nrows, cur, fin_com != 0, gs));
+                HIP_TRY(launch_finalize(gr.maxm, insts, gr.rows, gr.nrows, cur, fin_com != 0,
+                                        true, gs));
             }
         }
         if (forked)
@@ -595,7 +602,8 @@ int enqueue_loop(fjofc_ctx *ctx, const InstDesc *insts, int count, int maxm,
         }
         {
             Timed tm(ctx, K_FIN, 0.0, s);
-            HIP_TRY(launch_finalize(maxm, insts, rows, nrows, p & 1, next_due, s));
+            HIP_TRY(launch_finalize(maxm, insts, rows, nrows, p & 1, next_due,
+                                    nrows >= kFinOneThreadItems, s));
         }
         if (hook && (p + 1) % kChunk == 0 && p + 1 < iters) {
             bool stop = false;

@@ -8,15 +8,18 @@
 namespace fjofc {
 namespace {
 
-// FIN_SLICES threads per (row j, component k): slice s sums the slots
-// congruent to s mod FIN_SLICES; slice 0 adds the slices in order and does
-// the FP64 combine.
-template <int MM>
-__global__ __launch_bounds__(FIN_ROWS *FIN_SLICES) void finalize_kernel(
+// TPR threads per (row j, component k).  With TPR = FIN_SLICES, thread
+// slice s sums the slots congruent to s mod FIN_SLICES and slice 0 adds the
+// slices in order; with TPR = 1 one thread forms the same slice sums one
+// after the other and adds them in the same order, so both give the same
+// bits.  The thread with slice 0 does the FP64 combine.
+template <int MM, int TPR>
+__global__ __launch_bounds__(FIN_ROWS *TPR) void finalize_kernel(
     const InstDesc *__restrict__ insts, const RowItem *__restrict__ rows, int cur,
     int want_com) {
-    __shared__ double part[FIN_SLICES][FIN_ROWS];
-    __shared__ double sh[FIN_ROWS * FIN_SLICES / WAVE];
+    static_assert(TPR == 1 || TPR == FIN_SLICES, "one thread or one per slice");
+    __shared__ double part[TPR][FIN_ROWS];
+    __shared__ double sh[FIN_ROWS * TPR / WAVE];
     const RowItem ri = rows[blockIdx.x];
     const InstDesc &b = insts[ri.inst];
     if (b.st->done) return;
@@ -25,14 +28,20 @@ __global__ __launch_bounds__(FIN_ROWS *FIN_SLICES) void finalize_kernel(
     const int j = ri.bx * FIN_ROWS + r;
     double bx[MM];
     for (int q = 0; q < m; ++q) {
-        part[sl][r] = fin_slice(b, q, k, j, sl);
-        __syncthreads();
-        if (sl == 0) {
-            double t = part[0][r];
-            for (int e = 1; e < FIN_SLICES; ++e) t += part[e][r];
+        if constexpr (TPR == 1) {
+            double t = fin_slice(b, q, k, j, 0);
+            for (int e = 1; e < FIN_SLICES; ++e) t += fin_slice(b, q, k, j, e);
             bx[q] = b.wmat[q * m + q] * t;
+        } else {
+            part[sl][r] = fin_slice(b, q, k, j, sl);
+            __syncthreads();
+            if (sl == 0) {
+                double t = part[0][r];
+                for (int e = 1; e < FIN_SLICES; ++e) t += part[e][r];
+                bx[q] = b.wmat[q * m + q] * t;
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
     const double com = sl == 0 ? fin_combine<MM>(b, k, j, cur, bx, want_com) : 0.0;
     if (want_com) {
@@ -151,16 +160,25 @@ hipError_t launch_stream(int D, int variant, int vec4, const InstDesc *insts,
     return launch_stream_hi(D, variant, vec4, insts, items, nitems, cur, stress, acc, lds, s);
 }
 
-hipError_t launch_finalize(int maxm, const InstDesc *insts, const RowItem *rows, int nrows,
-                           int cur, bool want_com, hipStream_t s) {
-    if (nrows == 0) return hipSuccess;
-    const dim3 grid((unsigned)nrows), block(FIN_ROWS * FIN_SLICES);
+template <int TPR>
+static void finalize_tpr(int maxm, const InstDesc *insts, const RowItem *rows, int nrows,
+                         int cur, bool want_com, hipStream_t s) {
+    const dim3 grid((unsigned)nrows), block(FIN_ROWS * TPR);
     if (maxm <= 4)
-        finalize_kernel<4><<<grid, block, 0, s>>>(insts, rows, cur, want_com);
+        finalize_kernel<4, TPR><<<grid, block, 0, s>>>(insts, rows, cur, want_com);
     else if (maxm <= 8)
-        finalize_kernel<8><<<grid, block, 0, s>>>(insts, rows, cur, want_com);
+        finalize_kernel<8, TPR><<<grid, block, 0, s>>>(insts, rows, cur, want_com);
     else
-        finalize_kernel<MAXM><<<grid, block, 0, s>>>(insts, rows, cur, want_com);
+        finalize_kernel<MAXM, TPR><<<grid, block, 0, s>>>(insts, rows, cur, want_com);
+}
+
+hipError_t launch_finalize(int maxm, const InstDesc *insts, const RowItem *rows, int nrows,
+                           int cur, bool want_com, bool one_thread, hipStream_t s) {
+    if (nrows == 0) return hipSuccess;
+    if (one_thread)
+        finalize_tpr<1>(maxm, insts, rows, nrows, cur, want_com, s);
+    else
+        finalize_tpr<FIN_SLICES>(maxm, insts, rows, nrows, cur, want_com, s);
     return hipGetLastError();
 }
 
