@@ -183,9 +183,17 @@ __attribute__((amdgpu_waves_per_eu(MAXD <= 5 ? 4 : 2, 8))) void batch_kernel(Bat
                                               (int)((unsigned long long)sh_q >> 32)) << 32) |
                                         (unsigned)__builtin_amdgcn_readfirstlane((int)sh_q));
         if (q >= a.ntasks) break;
-        int t, pos;
-        batch_task_at(q, a.L, t, pos);
+        int period, pos;
+        batch_task_at(q, a.L, period, pos);
         const BatchTask tk = a.tmpl[pos];
+        const int t = period - tk.lag;
+        if (!batch_task_live(tk.kind, t, a.iters)) {
+            // no such transform: nothing to wait for, run or count (the
+            // barrier keeps wavefront 0 from overwriting sh_q before every
+            // wavefront has read it)
+            __syncthreads();
+            continue;
+        }
         const InstDesc &b = a.insts[tk.inst];
         int *c = &a.ctr[tk.inst].s_done;  // s_done, r_done, f_done
         const BatchDep dep = batch_dep(tk.kind, t, b.bnst, b.bnfin);

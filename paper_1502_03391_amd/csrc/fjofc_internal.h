@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 struct fjofc_ctx;
 
 namespace fjofc {
@@ -146,10 +148,18 @@ hipError_t launch_to_soa(const TriGeom &g, int D, const float *X, float *Xs,
 //   stream (t): f_done >= t bnfin   (X_t complete)
 //   reduce (t): s_done >= (t+1) bnst (every tile of transform t streamed)
 //   finalize (t): r_done >= t + 1   (transform t's reduce, hence its streams)
-// The order is transform by transform: [stream tasks][one reduce task per
-// problem][finalize tasks], the same template each transform (`tmpl`, L
-// tasks), and a last pass of streams and reduces at t = iters (the stress
-// of the returned configuration).  Every dependency of a task lies earlier
+// The queue repeats one template (`tmpl`, L tasks) per period.  The
+// problems, largest first, are dealt into three groups (rank mod 3), and a
+// period is
+//   [streams of group 0][reduces and finalizes of group 2, one period late]
+//   [streams of group 1][reduces and finalizes of group 0]
+//   [streams of group 2][reduces and finalizes of group 1]
+// so that between a task and the tasks it waits for lies another group's
+// stream block: workgroups find ready work while a group's finalize waits
+// for its last tiles.  A task's transform is the period minus its lag; the
+// queue runs iters + 2 periods and skips the tasks of transforms that do not
+// exist (batch_task_live).  Streams and reduces at t = iters give the stress
+// of the returned configuration.  Every dependency of a task lies earlier
 // in the order, so with all workgroups resident the earliest unfinished
 // task can always run.
 constexpr int BATCH_BLOCK = 256;
@@ -158,6 +168,7 @@ struct BatchTask {
     int kind, inst;
     int first;   // stream: first item (tile) index; finalize: first row item
     int count;   // tiles or row items of the group (1 for a reduce)
+    int lag;     // periods the task trails its period (its transform: period - lag)
 };
 struct BatchCtr {
     int s_done, r_done, f_done, pad;
@@ -174,18 +185,55 @@ __host__ __device__ inline BatchDep batch_dep(int kind, int t, int bnst, int bnf
     if (kind == BT_RED) return {0, (t + 1) * bnst, 1};  // transform t streamed
     return {1, t + 1, 2};                               // transform t reduced
 }
-// Task q of the sequence: transform q / L, template position q % L.
-__host__ __device__ inline void batch_task_at(long long q, int L, int &t, int &pos) {
-    t = (int)(q / L);
-    pos = (int)(q - (long long)t * L);
+// Task q of the sequence: period q / L, template position q % L.
+__host__ __device__ inline void batch_task_at(long long q, int L, int &period, int &pos) {
+    period = (int)(q / L);
+    pos = (int)(q - (long long)period * L);
+}
+// Whether the task of `kind` at transform t exists: streams and reduces for
+// t = 0..iters, finalizes for t < iters.
+__host__ __device__ inline bool batch_task_live(int kind, int t, int iters) {
+    return t >= 0 && t <= iters && !(kind == BT_FIN && t == iters);
+}
+// Periods of a run of `iters` transforms (the last one holds only the
+// lagging group's reduces at t = iters).
+inline long long batch_periods(int iters) { return (long long)iters + 2; }
+// The template (host side): st[p] and fin[p] are problem p's stream and
+// finalize tasks of one transform, `order` the problems largest first.
+inline std::vector<BatchTask> batch_template(const std::vector<int> &order,
+                                             const std::vector<std::vector<BatchTask>> &st,
+                                             const std::vector<std::vector<BatchTask>> &fin) {
+    std::vector<BatchTask> out;
+    auto streams = [&](int g) {
+        for (size_t r = g; r < order.size(); r += 3)
+            for (BatchTask tk : st[order[r]]) {
+                tk.lag = 0;
+                out.push_back(tk);
+            }
+    };
+    auto closes = [&](int g, int lag) {
+        for (size_t r = g; r < order.size(); r += 3) out.push_back({BT_RED, order[r], 0, 1, lag});
+        for (size_t r = g; r < order.size(); r += 3)
+            for (BatchTask tk : fin[order[r]]) {
+                tk.lag = lag;
+                out.push_back(tk);
+            }
+    };
+    streams(0);
+    closes(2, 1);
+    streams(1);
+    closes(0, 0);
+    streams(2);
+    closes(1, 0);
+    return out;
 }
 struct BatchArgs {
     const InstDesc *insts;
     const StreamItem *items;
     const RowItem *rows;
     const BatchTask *tmpl;
-    int L, Lsr;           // template length; its stream + reduce prefix
-    long long ntasks;     // iters L + Lsr
+    int L, pad0;          // template length
+    long long ntasks;     // batch_periods(iters) L
     BatchCtr *ctr;        // per problem
     int *head;            // next task
     int *err;             // non-zero: a wait timed out (the launch stops)
@@ -210,8 +258,9 @@ int batch_resident_blocks(int maxd, int maxm, size_t lds);
 // that the last ones of a transform run alone.  On the uneven 512-problem
 // batch with 256 x 512 tiles for every problem, a sweep of 12 settings
 // ranked (32, 8, 16) first (0.236 s; (32, 8, 8) 0.249 s, (32, 8, 32)
-// 0.253 s, (64, 16, 16) 0.292 s); with the tile cache's tiles it takes
-// 0.289 s against 0.300 s for (16, 4, 4).
+// 0.253 s, (64, 16, 16) 0.292 s); with the tile cache's tiles it took
+// 0.289 s against 0.300 s for (16, 4, 4) (both in the earlier one-group
+// order; the three-group order takes it to 0.262 s).
 constexpr int BATCH_TILES_1W = 32, BATCH_TILES_SHARED = 8, BATCH_ROWS = 16;
 // Dynamic LDS one persistent workgroup needs for a problem's stream tasks.
 size_t batch_stream_lds(int D, int variant, size_t tile_lds);

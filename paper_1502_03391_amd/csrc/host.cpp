@@ -982,7 +982,7 @@ namespace {
 int enqueue_persistent(fjofc_batch *b, int iters, double tol, int tol_mode, int stress_every) {
     hipStream_t s = b->cs;
     BatchArgs a = b->pargs;
-    a.ntasks = (long long)iters * a.L + a.Lsr;
+    a.ntasks = batch_periods(iters) * a.L;
     a.iters = iters;
     a.every = stress_every;
     a.tol = tol;
@@ -1240,10 +1240,9 @@ int fjofc_batch_create(fjofc_ctx *ctx, const fjofc_problem *probs, int count,
         r[1] = (int)rows.size() - r[0];
         grows[kv.first] = r;
     }
-    // Persistent plan: per problem (largest first) its stream tasks (four
-    // one-wavefront tiles or one shared tile each) and finalize row items;
-    // the template is [all stream tasks][one reduce per problem][all
-    // finalize tasks].
+    // Persistent plan: per problem (largest first) its stream tasks (groups
+    // of one-wavefront or shared tiles) and finalize tasks (groups of row
+    // items), arranged by batch_template.
     b->persist_ok = true;
     for (int p = 0; p < count; ++p) {
         if (!batch_variant_ok(b->hi[p].g.variant)) b->persist_ok = false;
@@ -1251,7 +1250,7 @@ int fjofc_batch_create(fjofc_ctx *ctx, const fjofc_problem *probs, int count,
     }
     std::vector<StreamItem> pitems;
     std::vector<RowItem> prows;
-    std::vector<BatchTask> tstream, tred, tfin;
+    std::vector<std::vector<BatchTask>> tstream(count), tfin(count);
     std::vector<int> nst(count, 0), nfin(count, 0);
     if (b->persist_ok) {
         for (int p : order) {
@@ -1261,16 +1260,15 @@ int fjofc_batch_create(fjofc_ctx *ctx, const fjofc_problem *probs, int count,
             const int per = h.g.variant <= 1 ? BATCH_TILES_1W : BATCH_TILES_SHARED;
             for (size_t q = 0; q < its.size(); q += per) {
                 const int cnt = (int)std::min<size_t>(per, its.size() - q);
-                tstream.push_back({BT_STREAM, p, (int)(pitems.size() + q), cnt});
+                tstream[p].push_back({BT_STREAM, p, (int)(pitems.size() + q), cnt, 0});
             }
             nst[p] = (int)its.size();
             pitems.insert(pitems.end(), its.begin(), its.end());
-            tred.push_back({BT_RED, p, 0, 1});
             std::vector<RowItem> rs;
             append_rows(p, h, rs);
             for (size_t q = 0; q < rs.size(); q += BATCH_ROWS) {
                 const int cnt = (int)std::min<size_t>(BATCH_ROWS, rs.size() - q);
-                tfin.push_back({BT_FIN, p, (int)(prows.size() + q), cnt});
+                tfin[p].push_back({BT_FIN, p, (int)(prows.size() + q), cnt, 0});
             }
             nfin[p] = (int)rs.size();
             prows.insert(prows.end(), rs.begin(), rs.end());
@@ -1284,10 +1282,8 @@ int fjofc_batch_create(fjofc_ctx *ctx, const fjofc_problem *probs, int count,
         b->pgrid = per_cu * ncu;
         if (b->pgrid < 1) b->persist_ok = false;
     }
-    std::vector<BatchTask> tmpl;
-    tmpl.insert(tmpl.end(), tstream.begin(), tstream.end());
-    tmpl.insert(tmpl.end(), tred.begin(), tred.end());
-    tmpl.insert(tmpl.end(), tfin.begin(), tfin.end());
+    const std::vector<BatchTask> tmpl =
+        b->persist_ok ? batch_template(order, tstream, tfin) : std::vector<BatchTask>();
 
     Carve cv;
     const size_t o_insts = cv.take<InstDesc>(count);
@@ -1347,7 +1343,6 @@ int fjofc_batch_create(fjofc_ctx *ctx, const fjofc_problem *probs, int count,
         a.rows = reinterpret_cast<const RowItem *>(base + o_prows);
         a.tmpl = reinterpret_cast<const BatchTask *>(base + o_tmpl);
         a.L = (int)tmpl.size();
-        a.Lsr = (int)(tstream.size() + tred.size());
         a.ctr = reinterpret_cast<BatchCtr *>(base + o_ctr);
         long long *flags = reinterpret_cast<long long *>(base + o_flags);
         a.head = reinterpret_cast<int *>(flags);

@@ -10,6 +10,7 @@
 // after the reduce and every stream task of t.
 #include "fjofc_internal.h"
 
+#include <algorithm>
 #include <cstdio>
 #include <random>
 #include <vector>
@@ -36,22 +37,20 @@ int main() {
             nfin[p] = 1 + (int)(rng() % 12);
         }
         const int gs = 1 + (int)(rng() % 16), gf = 1 + (int)(rng() % 4);
-        // template: [stream groups of every problem][one reduce per problem]
-        // [finalize groups of every problem], problems in a shuffled order
+        // the kernel's template (batch_template), problems in a shuffled order
         std::vector<int> order(count);
         for (int p = 0; p < count; ++p) order[p] = p;
         std::shuffle(order.begin(), order.end(), rng);
-        std::vector<BatchTask> tmpl;
-        for (int p : order)
+        std::vector<std::vector<BatchTask>> st(count), fin(count);
+        for (int p = 0; p < count; ++p) {
             for (int k = 0; k < nst[p]; k += gs)
-                tmpl.push_back({BT_STREAM, p, k, std::min(gs, nst[p] - k)});
-        for (int p : order) tmpl.push_back({BT_RED, p, 0, 1});
-        const int Lsr = (int)tmpl.size();
-        for (int p : order)
+                st[p].push_back({BT_STREAM, p, k, std::min(gs, nst[p] - k), 0});
             for (int k = 0; k < nfin[p]; k += gf)
-                tmpl.push_back({BT_FIN, p, k, std::min(gf, nfin[p] - k)});
+                fin[p].push_back({BT_FIN, p, k, std::min(gf, nfin[p] - k), 0});
+        }
+        const std::vector<BatchTask> tmpl = batch_template(order, st, fin);
         const int L = (int)tmpl.size();
-        const long long ntasks = (long long)iters * L + Lsr;
+        const long long ntasks = batch_periods(iters) * L;
         // counters (as the kernel keeps them) and the independent record of
         // completed tasks per (problem, transform, kind)
         std::vector<std::array<int, 3>> ctr(count, {0, 0, 0});
@@ -67,9 +66,17 @@ int main() {
             for (Worker &w : ws) {
                 if (w.q < 0 && head < ntasks) w.q = head++;
                 if (w.q < 0 || w.running) continue;
-                int t, pos;
-                batch_task_at(w.q, L, t, pos);
+                int period, pos;
+                batch_task_at(w.q, L, period, pos);
                 const BatchTask &tk = tmpl[pos];
+                const int t = period - tk.lag;
+                if (!batch_task_live(tk.kind, t, iters)) {
+                    // skipped at once, as the kernel does
+                    w.q = -1;
+                    ++completed;
+                    progressed = true;
+                    continue;
+                }
                 const BatchDep dep = batch_dep(tk.kind, t, nst[tk.inst], nfin[tk.inst]);
                 if (ctr[tk.inst][dep.wait] < dep.need) continue;  // waits
                 // the method's order
@@ -102,9 +109,10 @@ int main() {
                 continue;
             }
             now = first->end;
-            int t, pos;
-            batch_task_at(first->q, L, t, pos);
+            int period, pos;
+            batch_task_at(first->q, L, period, pos);
             const BatchTask &tk = tmpl[pos];
+            const int t = period - tk.lag;
             const BatchDep dep = batch_dep(tk.kind, t, nst[tk.inst], nfin[tk.inst]);
             ctr[tk.inst][dep.done] += tk.count;
             doneby[tk.inst][t][tk.kind == BT_STREAM ? 0 : (tk.kind == BT_RED ? 1 : 2)] +=
@@ -113,6 +121,18 @@ int main() {
             first->q = -1;
             ++completed;
         }
+        // every task of every transform ran exactly once: streams and
+        // reduces for t = 0..iters, finalizes for t < iters
+        for (int p = 0; p < count && ok; ++p)
+            for (int t = 0; t <= iters; ++t) {
+                const auto &d = doneby[p][t];
+                if (d[0] != nst[p] || d[1] != 1 || d[2] != (t < iters ? nfin[p] : 0)) {
+                    std::printf("trial %d: problem %d transform %d ran %d/%d/%d tasks\n", trial,
+                                p, t, d[0], d[1], d[2]);
+                    ok = false;
+                    break;
+                }
+            }
         ++runs;
         if (!ok) ++fails;
     }
