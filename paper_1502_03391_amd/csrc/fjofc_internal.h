@@ -252,16 +252,15 @@ hipError_t launch_batch_persistent(const BatchArgs &a, int maxd, int maxm, int g
 // Workgroups of the persistent kernel one CU holds at once (0 on error).
 int batch_resident_blocks(int maxd, int maxm, size_t lds);
 // Tiles per stream task: one-wavefront tiles, eight per wavefront; shared
-// tiles, eight in turn.  Finalize row items per task.  Every task ends in
+// tiles, twelve in turn.  Finalize row items per task.  Every task ends in
 // an agent-scope release and starts after an acquire, and a task that must
 // wait holds its workgroup, so tasks are made coarse, but not so coarse
-// that the last ones of a transform run alone.  On the uneven 512-problem
-// batch with 256 x 512 tiles for every problem, a sweep of 12 settings
-// ranked (32, 8, 16) first (0.236 s; (32, 8, 8) 0.249 s, (32, 8, 32)
-// 0.253 s, (64, 16, 16) 0.292 s); with the tile cache's tiles it took
-// 0.289 s against 0.300 s for (16, 4, 4) (both in the earlier one-group
-// order; the three-group order takes it to 0.262 s).
-constexpr int BATCH_TILES_1W = 32, BATCH_TILES_SHARED = 8, BATCH_ROWS = 16;
+// that the last ones of a block run alone.  On the uneven 512-problem batch
+// with the tile cache's tiles, in the three-group order, sweeps ranked
+// (32, 12, 8) first at 0.250 s (same box: (32, 16, 12) 0.250 s, (40, 16, 8)
+// 0.255 s, (32, 8, 8) 0.256 s, (32, 8, 16) 0.262 s, (16, 4, 8) 0.284 s,
+// (32, 24, 8) 0.286 s).
+constexpr int BATCH_TILES_1W = 32, BATCH_TILES_SHARED = 12, BATCH_ROWS = 8;
 // Dynamic LDS one persistent workgroup needs for a problem's stream tasks.
 size_t batch_stream_lds(int D, int variant, size_t tile_lds);
 // Kernel variants the persistent kernel runs (one-wavefront 4 x 8 tiles,
