@@ -524,13 +524,14 @@ def bench_batched(ctx, iters=150, launches=("lockstep", "persistent")):
             X.copy_(X0)
         torch.cuda.synchronize()
 
-    def timed(launch):
+    def timed(launch, quiet=False):
         b = fjofc.Batch(ctx, probs)
         try:
             b.set_launch(launch)
         except fjofc.FjofcError as e:
             b.close()
-            print(f"[bench] batched: no {launch} launch: {e}", file=sys.stderr, flush=True)
+            if not quiet:
+                print(f"[bench] batched: no {launch} launch: {e}", file=sys.stderr, flush=True)
             return None
         reset()
         b.run(iters, stress_every=iters, want_results=False)
@@ -588,10 +589,14 @@ def bench_batched(ctx, iters=150, launches=("lockstep", "persistent")):
     msg = f"{launches[0]} {sec:.4f} s"
     if "persistent" in launches[1:]:
         ref = first
-        pers = timed("persistent")
+        pers = timed("persistent", quiet=True)
         if pers is None:
             # compare both launches on one plan the persistent kernel runs
             retiled = persistent_retiling()
+            print(f"[bench] batched: {retiled[1]} problems of the cache's plan have 8-column "
+                  "tiles, which the persistent launch has no form of; both launches are "
+                  "compared on the plan with those problems on the 4-column tile",
+                  file=sys.stderr, flush=True)
             ref = timed_on(retiled[0], "lockstep")
             pers = timed_on(retiled[0], "persistent")
             r["persistent_plan"] = {"problems_retiled": retiled[1],
