@@ -407,9 +407,6 @@ hipError_t launch_validate_rows(const float *d, long long count, unsigned long l
 
 // Records the calling thread's error message (host.cpp); returns `code`.
 int set_error(int code, const char *fmt, ...);
-// Context services for entry points outside host.cpp: its device, its
-// device workspace (grown to at least `bytes`; contents not preserved) and
-// its pinned host staging buffer.
 // Kinds of timed work of the per-kernel profile (fjofc_profile_*).
 enum ProfKind { K_STREAM = 0, K_EDGE, K_FIN, K_RED, K_OOS, K_BATCH, K_INIT, K_KINDS };
 // Brackets what is enqueued on s during its lifetime with HIP events when
@@ -423,6 +420,9 @@ struct Timed {
     Timed(fjofc_ctx *c_, int kind_, double bytes_, hipStream_t s_);
     ~Timed();
 };
+// Context services for entry points outside host.cpp: its device, its
+// device workspace (grown to at least `bytes`; contents not preserved) and
+// its pinned host staging buffer.
 int ctx_device(const fjofc_ctx *ctx);
 int ctx_workspace(fjofc_ctx *ctx, size_t bytes, void **ws);
 int ctx_pinned(fjofc_ctx *ctx, size_t bytes, void **p);
