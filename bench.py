@@ -548,13 +548,14 @@ def bench_batched(ctx, iters=150, launches=("lockstep", "persistent")):
         return min(times), res, out
 
     def persistent_retiling():
-        # problems whose cached tile has 8 columns per lane, which the
-        # persistent kernel has no form of, take the 4-column tile of the
-        # same height: scoped FJOFC_TILE entries, and how many problems
+        # problems whose cached tile has 8 columns per lane or double-buffered
+        # loads, which the persistent kernel has no form of, take the
+        # single-buffered 4-column tile of the same height: scoped FJOFC_TILE
+        # entries, and how many problems
         swap, k = set(), 0
         for sp in specs:
             th, var = fjofc.fjofc_tile_choice(ctx, sp.n, sp.d)
-            if var in (2, 3):
+            if var in (0, 2, 3):
                 swap.add(f"{sp.d}:{sp.n}:{sp.n}:{th}:1")
                 k += 1
         return ",".join(sorted(swap)), k
@@ -594,8 +595,9 @@ def bench_batched(ctx, iters=150, launches=("lockstep", "persistent")):
             # compare both launches on one plan the persistent kernel runs
             retiled = persistent_retiling()
             print(f"[bench] batched: {retiled[1]} problems of the cache's plan have 8-column "
-                  "tiles, which the persistent launch has no form of; both launches are "
-                  "compared on the plan with those problems on the 4-column tile",
+                  "or double-buffered tiles, which the persistent launch has no form of; both "
+                  "launches are compared on the plan with those problems on the single-buffered "
+                  "4-column tile",
                   file=sys.stderr, flush=True)
             ref = timed_on(retiled[0], "lockstep")
             pers = timed_on(retiled[0], "persistent")

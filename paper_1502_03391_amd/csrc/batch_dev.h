@@ -14,23 +14,21 @@ namespace {
 
 // One tile of a stream group: the same code as the lockstep kernel (results
 // are bitwise equal), with the row points read coherently.  One-wavefront
-// tiles (variants 0 and 1, with and without double-buffered row loads) run
-// on the calling wavefront and its LDS slice, shared tiles (variants 4 and
-// 5) on the whole workgroup.
+// tiles (variant 1) run on the calling wavefront and its LDS slice, shared
+// tiles (variants 4 and 5) on the whole workgroup.
 template <int D, int VAR, bool VEC4, bool STRESS>
 __device__ __forceinline__ void batch_tile(const InstDesc *__restrict__ insts,
                                            const StreamItem &it, int cur, lfloat *smem) {
     constexpr int R = VAR == 4 ? 4 : (VAR == 5 ? 2 : 1);
     constexpr int C = VAR == 5 ? 2 : 1;
-    constexpr bool DB = VAR == 0;
     const InstDesc &b = insts[it.inst];
     const float *Xs = b.Xs[cur];
     const int I = it.tile >> 16, J = it.tile & 0xffff;
     if (it.ftile < b.g.nint)
-        stream_tile<D, 4, 8, DB, VEC4, false, STRESS, true, R, C, true>(
+        stream_tile<D, 4, 8, false, VEC4, false, STRESS, true, R, C, true>(
             b.g, b.dp, Xs, it.mod, I, J, it.ftile, b.P, b.F, smem);
     else
-        stream_tile<D, 4, 8, DB, VEC4, true, STRESS, true, R, C, true>(
+        stream_tile<D, 4, 8, false, VEC4, true, STRESS, true, R, C, true>(
             b.g, b.dp, Xs, it.mod, I, J, it.ftile, b.P, b.F, smem);
 }
 
@@ -42,7 +40,7 @@ template <int D, int VAR, bool VEC4, bool STRESS>
 __device__ __forceinline__ void batch_stream(const InstDesc *__restrict__ insts,
                                              const StreamItem *__restrict__ items, int count,
                                              int cur, lfloat *smem) {
-    if constexpr (VAR == 0 || VAR == 1) {
+    if constexpr (VAR == 1) {
         const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
         lfloat *ws = smem + (size_t)w * 4 * D * WAVE;
         for (int q = w; q < count; q += BATCH_BLOCK / WAVE)
@@ -62,8 +60,7 @@ __device__ __forceinline__ void batch_stream_d(int variant, int vec4, bool stres
 #define FJOFC_BS(V, V4, S)                                                          \
     if (variant == V && (vec4 != 0) == V4 && stress == S)                           \
         return batch_stream<D, V, V4, S>(insts, items, count, cur, smem);
-    FJOFC_BS(0, false, false) FJOFC_BS(0, false, true) FJOFC_BS(0, true, false)
-    FJOFC_BS(0, true, true) FJOFC_BS(1, false, false) FJOFC_BS(1, false, true) FJOFC_BS(1, true, false)
+    FJOFC_BS(1, false, false) FJOFC_BS(1, false, true) FJOFC_BS(1, true, false)
     FJOFC_BS(1, true, true) FJOFC_BS(4, false, false) FJOFC_BS(4, false, true)
     FJOFC_BS(4, true, false) FJOFC_BS(4, true, true) FJOFC_BS(5, false, false)
     FJOFC_BS(5, false, true) FJOFC_BS(5, true, false) FJOFC_BS(5, true, true)

@@ -263,10 +263,13 @@ int batch_resident_blocks(int maxd, int maxm, size_t lds);
 constexpr int BATCH_TILES_1W = 32, BATCH_TILES_SHARED = 12, BATCH_ROWS = 8;
 // Dynamic LDS one persistent workgroup needs for a problem's stream tasks.
 size_t batch_stream_lds(int D, int variant, size_t tile_lds);
-// Kernel variants the persistent kernel runs (one-wavefront 4 x 8 tiles,
-// with or without double-buffered loads, and 4 x 1 and 2 x 2 shared tiles).
+// Kernel variants the persistent kernel runs: one-wavefront 4 x 8 tiles
+// (single-buffered) and 4 x 1 and 2 x 2 shared tiles.  The double-buffered
+// and 8-column tiles need more registers than the kernel's other paths, and
+// inlined into its one function they made it spill (1468 VGPRs with the
+// double-buffered form; without it the launch was 7% faster).
 inline bool batch_variant_ok(int variant) {
-    return variant == 0 || variant == 1 || variant == 4 || variant == 5;
+    return variant == 1 || variant == 4 || variant == 5;
 }
 
 // ---- launchers (oos.hip) ---------------------------------------------

@@ -52,17 +52,22 @@ LAUNCHES = ["lockstep", "persistent"]
 
 
 @pytest.mark.parametrize("launch", LAUNCHES)
-@pytest.mark.parametrize("tile", [None, "64:4", "96:5", "128:0"])
+@pytest.mark.parametrize("tile", [None, "64:4", "96:5", "128:1", "128:0"])
 def test_batch_equals_standalone_and_oracle(ctx, monkeypatch, tile, launch):
     """Also with every instance forced onto a multi-wavefront tile variant,
     whose launches size their LDS for the tallest tile of the batch, or onto
-    the double-buffered one-wavefront variant (which the persistent launch
-    runs in its single-buffer form: same sums, so still bitwise equal)."""
+    a one-wavefront variant, single- or double-buffered (the persistent
+    launch has no double-buffered form and refuses that plan)."""
     if tile:
         monkeypatch.setenv("FJOFC_TILE", tile)
     insts = _instances(12)
     iters = 40
     dev = [([_dev(x) for x in dl], w, _dev(X0)) for _, dl, w, X0 in insts]
+    if launch == "persistent" and tile == "128:0":
+        with pytest.raises(fjofc.FjofcError) as e:
+            fjofc.Batch(ctx, dev, launch=launch)
+        assert e.value.code == 1
+        return
     b = fjofc.Batch(ctx, dev, launch=launch)
     res = b.run(iters, stress_every=iters)
     torch.cuda.synchronize()
@@ -204,11 +209,13 @@ def test_persistent_and_lockstep_batches_agree(ctx):
     b.close()
 
 
-def test_persistent_launch_refuses_other_variants(ctx, monkeypatch):
-    """Tiles of 8 columns per lane (variants 2 and 3) have no persistent
-    form: selecting the persistent launch for such a batch returns
-    FJOFC_EINVAL and leaves the plan usable in lockstep."""
-    monkeypatch.setenv("FJOFC_TILE", "64:2")
+@pytest.mark.parametrize("tile", ["64:2", "64:3", "64:0"])
+def test_persistent_launch_refuses_other_variants(ctx, monkeypatch, tile):
+    """Tiles of 8 columns per lane (variants 2 and 3) and double-buffered
+    tiles (variant 0) have no persistent form: selecting the persistent
+    launch for such a batch returns FJOFC_EINVAL and leaves the plan usable
+    in lockstep."""
+    monkeypatch.setenv("FJOFC_TILE", tile)
     insts = _instances(3, seed=29, n_lo=30, n_hi=200)
     dev = [([_dev(x) for x in dl], w, _dev(X0)) for _, dl, w, X0 in insts]
     b = fjofc.Batch(ctx, dev)
