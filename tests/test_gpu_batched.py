@@ -209,6 +209,35 @@ def test_persistent_and_lockstep_batches_agree(ctx):
     b.close()
 
 
+def test_persistent_batch_wider_tier(ctx):
+    """Problems with d = 6..8 run in the persistent kernel's D <= 8 tier:
+    bitwise equal to the lockstep graph and within tolerance of the oracle,
+    beside d = 2 problems of the same batch."""
+    shapes = [(2, 150, 6), (3, 97, 7), (2, 260, 8), (3, 64, 6), (2, 333, 8), (3, 120, 2)]
+    insts = []
+    for i, (m, n, d) in enumerate(shapes):
+        sp = gen.BatchedSpec(i, m, n, d, 0.1, 5000 + i)
+        views, _, X0 = gen.instance_views(sp)
+        delta = [gen.pairwise_dist_np(Y).astype(np.float32) for Y in views]
+        insts.append((sp, delta, gen.uniform_wmat(m, 0.5), X0.astype(np.float32)))
+    iters = 30
+    out = {}
+    for mode in ("persistent", "lockstep"):
+        dev = [([_dev(x) for x in dl], w, _dev(X0)) for _, dl, w, X0 in insts]
+        b = fjofc.Batch(ctx, dev, launch=mode)
+        res = b.run(iters, stress_every=iters)
+        torch.cuda.synchronize()
+        out[mode] = ([X.clone() for _, _, X in dev], res)
+        b.close()
+    for Xp, Xl in zip(out["persistent"][0], out["lockstep"][0]):
+        assert torch.equal(Xp, Xl)
+    assert out["persistent"][1] == out["lockstep"][1]
+    for (sp, dl, w, X0), Xb, r in zip(insts, out["persistent"][0], out["persistent"][1]):
+        Xo, ro, _ = orc.embed(dl, w, X0, iters, stress_every=iters)
+        assert r["stress"] == pytest.approx(ro["stress"], rel=1e-5), sp.d
+        assert _rel_fro(Xb.cpu().numpy().astype(np.float64), Xo) <= 1e-4, sp.d
+
+
 @pytest.mark.parametrize("tile", ["64:2", "64:3", "64:0"])
 def test_persistent_launch_refuses_other_variants(ctx, monkeypatch, tile):
     """Tiles of 8 columns per lane (variants 2 and 3) and double-buffered
