@@ -238,6 +238,35 @@ def test_persistent_batch_wider_tier(ctx):
         assert _rel_fro(Xb.cpu().numpy().astype(np.float64), Xo) <= 1e-4, sp.d
 
 
+@pytest.mark.parametrize("launch", LAUNCHES)
+def test_batch_many_modalities(ctx, launch):
+    """Problems with m = 6 and m = 9 beside m = 2 (the finalize's m <= 8
+    and m <= 32 forms, in the branch and the persistent finalizes): every
+    problem equals its standalone run bitwise and the oracle within
+    tolerance."""
+    shapes = [(2, 90, 3), (6, 70, 2), (9, 45, 5), (6, 111, 5), (2, 64, 2)]
+    insts = []
+    for i, (m, n, d) in enumerate(shapes):
+        sp = gen.BatchedSpec(i, m, n, d, 0.15, 6000 + i)
+        views, _, X0 = gen.instance_views(sp)
+        delta = [gen.pairwise_dist_np(Y).astype(np.float32) for Y in views]
+        insts.append((sp, delta, gen.uniform_wmat(m, 0.5), X0.astype(np.float32)))
+    iters = 20
+    dev = [([_dev(x) for x in dl], w, _dev(X0)) for _, dl, w, X0 in insts]
+    b = fjofc.Batch(ctx, dev, launch=launch)
+    res = b.run(iters, stress_every=iters)
+    torch.cuda.synchronize()
+    for (sp, dl, w, X0), (dd, _, Xb), r in zip(insts, dev, res):
+        Xs = _dev(X0)
+        rs, _ = fjofc.fjofc_embed(ctx, dd, w, Xs, iters, stress_every=iters)
+        assert torch.equal(Xb, Xs), f"m={sp.m} differs from standalone"
+        assert r["stress"] == rs["stress"]
+        Xo, ro, _ = orc.embed(dl, w, X0, iters, stress_every=iters)
+        assert r["stress"] == pytest.approx(ro["stress"], rel=1e-5)
+        assert _rel_fro(Xb.cpu().numpy().astype(np.float64), Xo) <= 1e-4
+    b.close()
+
+
 @pytest.mark.parametrize("tile", ["64:2", "64:3", "64:0"])
 def test_persistent_launch_refuses_other_variants(ctx, monkeypatch, tile):
     """Tiles of 8 columns per lane (variants 2 and 3) and double-buffered

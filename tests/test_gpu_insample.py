@@ -179,6 +179,21 @@ def test_many_iterations_parity_general_w(ctx):
     assert _rel_fro(Xg, Xo) <= 1e-4
 
 
+@pytest.mark.parametrize("m,n,d", [(5, 70, 3), (6, 130, 2), (8, 61, 4), (9, 41, 5),
+                                   (12, 33, 2)])
+def test_many_modalities_parity(ctx, m, n, d):
+    """m above 4 takes the finalize's wider forms (m <= 8 and m <= 32
+    register tiers): X and the stress after 12 transforms with a general
+    weight matrix, against the oracle."""
+    wmat = _general_wmat(m, seed=m + n)
+    delta, _, X0 = _problem(30 + m, m, n, d, wmat=wmat)
+    Xo, ro, _ = orc.embed(delta, wmat, X0, 12, stress_every=12)
+    Xg, rg, _ = _gpu_embed(ctx, delta, wmat, X0, 12, stress_every=12)
+    assert rg["iters_run"] == 12
+    assert rg["stress"] == pytest.approx(ro["stress"], rel=1e-5)
+    assert _rel_fro(Xg, Xo) <= 1e-4
+
+
 # (seed, tol_mode, tol, stress_every): cases whose every checkpoint decision
 # lies at least 1e-4 (relative to the previous stress) away from the
 # threshold in the oracle, so FP32 rounding cannot flip any of them.
