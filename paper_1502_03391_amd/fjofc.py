@@ -219,6 +219,26 @@ def fjofc_embed(ctx: Context, delta: Sequence, wmat, X, iters: int,
     return res.as_dict(), hist
 
 
+def fjofc_embed_w(ctx: Context, delta: Sequence, w: float, X, iters: int,
+                  tol: float = 0.0, tol_mode: int = FJOFC_TOL_REL,
+                  stress_every: int = 1, want_hist: bool = False, stream=None):
+    """In-sample fJOFC with the uniform weights of eq:W (w_ii = 1, w_ik = w).
+    Returns (result dict, stress history or None)."""
+    import torch
+    m = len(delta)
+    n = int(delta[0].shape[0])
+    ptrs = (C.c_void_p * m)(*[_dev_ptr(t, torch.float32, "delta") for t in delta])
+    d = int(X.shape[1])
+    res = FjofcResult()
+    hist = np.empty(iters + 1) if want_hist else None
+    hp = hist.ctypes.data_as(C.POINTER(C.c_double)) if want_hist else None
+    _check(lib().fjofc_embed_w(ctx.handle, ptrs, m, n, float(w), d,
+                               _dev_ptr(X, torch.float32, "X"), int(iters), float(tol),
+                               int(tol_mode), int(stress_every), hp, C.byref(res),
+                               _stream_ptr(stream)))
+    return res.as_dict(), hist
+
+
 def fjofc_init_cmds(ctx: Context, delta: Sequence, X, iters: int = 20, stream=None):
     """The paper's start X0: cMDS of the mean dissimilarity, cMDS of each
     Delta_i, Procrustes fit of each onto the first.  X: CUDA float32

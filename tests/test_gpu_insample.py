@@ -179,6 +179,25 @@ def test_many_iterations_parity_general_w(ctx):
     assert _rel_fro(Xg, Xo) <= 1e-4
 
 
+def test_uniform_weight_entry_point(ctx):
+    """fjofc_embed_w (eq:W's uniform weights) is fjofc_embed with the
+    matrix w_ii = 1, w_ik = w: bitwise the same X, stress and history, and
+    the oracle's result."""
+    m, n, d, w = 3, 150, 2, 0.7
+    delta, _, X0 = _problem(17, m, n, d)
+    dd = [_dev(x) for x in delta]
+    Xa, Xb = _dev(X0), _dev(X0)
+    ra, ha = fjofc.fjofc_embed_w(ctx, dd, w, Xa, 25, stress_every=5, want_hist=True)
+    rb, hb = fjofc.fjofc_embed(ctx, dd, gen.uniform_wmat(m, w), Xb, 25, stress_every=5,
+                               want_hist=True)
+    torch.cuda.synchronize()
+    assert torch.equal(Xa, Xb) and ra == rb and ra["iters_run"] == 25
+    np.testing.assert_array_equal(ha, hb)
+    Xo, ro, _ = orc.embed(delta, gen.uniform_wmat(m, w), X0, 25, stress_every=5)
+    assert ra["stress"] == pytest.approx(ro["stress"], rel=1e-5)
+    assert _rel_fro(Xa.cpu().numpy().astype(np.float64), Xo) <= 1e-4
+
+
 @pytest.mark.parametrize("m,n,d", [(5, 70, 3), (6, 130, 2), (8, 61, 4), (9, 41, 5),
                                    (12, 33, 2)])
 def test_many_modalities_parity(ctx, m, n, d):
