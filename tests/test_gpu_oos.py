@@ -94,6 +94,34 @@ def test_oos_parity(ctx, monkeypatch, m, n, d, k, ob, weights):
         np.testing.assert_allclose(Yg, Yo, rtol=0, atol=1e-4 * scale)
 
 
+def test_oos_empty_and_single_object_edges(ctx):
+    """k = 0 new objects is a no-op that succeeds; an in-sample set of one
+    object (n = 1, every sum over j has one term) and of two objects
+    match the oracle.  With so few terms an object's stress can fall near
+    0, where a relative bound is meaningless: FP32 positions (error eps
+    |y|) move a stress sigma by about 2 sqrt(sigma) eps |y|, so the bound is
+    1e-5 sigma + 1e-6 sqrt(sigma) max|delta|."""
+    m, d = 2, 3
+    X = np.random.default_rng(4).standard_normal((m * 5, d)).astype(np.float32)
+    wmat = gen.uniform_wmat(m, 0.5)
+    Y = torch.full((0, m, d), 7.0, device="cuda")
+    fjofc.fjofc_oos(ctx, _dev(X), wmat, torch.empty((0, m, 5), device="cuda"), Y, 10)
+    torch.cuda.synchronize()
+    for n in (1, 2):
+        rng = np.random.default_rng(10 + n)
+        Xn = rng.standard_normal((m * n, d)).astype(np.float32)
+        k = 6
+        dnew = rng.uniform(0.5, 3.0, (k, m, n)).astype(np.float32)
+        Y0 = rng.standard_normal((k, m, d)).astype(np.float32)
+        for iters in (1, 15):
+            Yo, so, io = orc.oos(Xn, wmat, dnew, Y0, iters)
+            Yg, sg, ig = _run(ctx, Xn, wmat, dnew, Y0, iters)
+            assert np.array_equal(ig, io), (n, iters)
+            bound = 1e-5 * so + 1e-6 * np.sqrt(so) * np.abs(dnew).max()
+            assert np.all(np.abs(sg - so) <= bound), (n, iters, sg, so)
+            np.testing.assert_allclose(Yg, Yo, rtol=0, atol=1e-4 * max(1.0, np.abs(Yo).max()))
+
+
 @pytest.mark.parametrize("ob", [None, "1"])
 def test_oos_target_and_tol_stops(ctx, monkeypatch, ob):
     if ob:
