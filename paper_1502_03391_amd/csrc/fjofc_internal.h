@@ -149,14 +149,13 @@ hipError_t launch_to_soa(const TriGeom &g, int D, const float *X, float *Xs,
 //   reduce (t): s_done >= (t+1) bnst (every tile of transform t streamed)
 //   finalize (t): r_done >= t + 1   (transform t's reduce, hence its streams)
 // The queue repeats one template (`tmpl`, L tasks) per period.  The
-// problems, largest first, are dealt into three groups (rank mod 3), and a
-// period is
-//   [streams of group 0][reduces and finalizes of group 2, one period late]
-//   [streams of group 1][reduces and finalizes of group 0]
-//   [streams of group 2][reduces and finalizes of group 1]
-// so that between a task and the tasks it waits for lies another group's
-// stream block: workgroups find ready work while a group's finalize waits
-// for its last tiles.  A task's transform is the period minus its lag; the
+// problems, largest first, are dealt into six groups (rank mod 6), and a
+// period is, for g = 0..5, the streams of group g followed by the reduces
+// and finalizes of group g - 3 (mod 6; one period late for g < 3).  So
+// between a group's streams and its reduces and finalizes lie three other
+// groups' stream blocks, and between those and the group's next streams
+// two more: workgroups find ready work while a group's finalize waits for
+// its last tiles.  A task's transform is the period minus its lag; the
 // queue runs iters + 2 periods and skips the tasks of transforms that do not
 // exist (batch_task_live).  Streams and reduces at t = iters give the stress
 // of the returned configuration.  Every dependency of a task lies earlier
@@ -200,31 +199,35 @@ __host__ __device__ inline bool batch_task_live(int kind, int t, int iters) {
 inline long long batch_periods(int iters) { return (long long)iters + 2; }
 // The template (host side): st[p] and fin[p] are problem p's stream and
 // finalize tasks of one transform, `order` the problems largest first.
+// On the uneven 512-problem batch (same box): 6 groups at distance 3 took
+// 0.225 s, 8 at 4 0.225 s, 4 at 2 0.229 s, 5 at 2 0.229 s, 3 at 1 0.233 s,
+// 6 at 2 0.237 s, 8 at 3 0.235 s.
+constexpr int BATCH_GROUPS = 6, BATCH_GROUP_DIST = 3;
 inline std::vector<BatchTask> batch_template(const std::vector<int> &order,
                                              const std::vector<std::vector<BatchTask>> &st,
                                              const std::vector<std::vector<BatchTask>> &fin) {
+    constexpr int NG = BATCH_GROUPS, DIST = BATCH_GROUP_DIST;
+    static_assert(DIST >= 1 && DIST < NG, "a group's closes follow its own streams");
     std::vector<BatchTask> out;
     auto streams = [&](int g) {
-        for (size_t r = g; r < order.size(); r += 3)
+        for (size_t r = g; r < order.size(); r += NG)
             for (BatchTask tk : st[order[r]]) {
                 tk.lag = 0;
                 out.push_back(tk);
             }
     };
     auto closes = [&](int g, int lag) {
-        for (size_t r = g; r < order.size(); r += 3) out.push_back({BT_RED, order[r], 0, 1, lag});
-        for (size_t r = g; r < order.size(); r += 3)
+        for (size_t r = g; r < order.size(); r += NG) out.push_back({BT_RED, order[r], 0, 1, lag});
+        for (size_t r = g; r < order.size(); r += NG)
             for (BatchTask tk : fin[order[r]]) {
                 tk.lag = lag;
                 out.push_back(tk);
             }
     };
-    streams(0);
-    closes(2, 1);
-    streams(1);
-    closes(0, 0);
-    streams(2);
-    closes(1, 0);
+    for (int g = 0; g < NG; ++g) {
+        streams(g);
+        closes((g - DIST + NG) % NG, g < DIST ? 1 : 0);
+    }
     return out;
 }
 struct BatchArgs {
