@@ -307,8 +307,11 @@ int fjofc_tile_choice(fjofc_ctx *ctx, int n, int d, int *tile_height, int *varia
  *     FJOFC_EHIP.  Both launches run the same tiles and sums: results are
  *     bitwise equal.
  * Returns FJOFC_EINVAL for an unknown value, or for the persistent launch
- * when a problem's tile shape has no persistent variant.  A change of launch
- * discards the captured graph (the next run captures again).              */
+ * when a problem's tile has no persistent form (the persistent kernel runs
+ * the single-buffered 4-column one-wavefront tile and the 4 x 1 and 2 x 2
+ * shared tiles, variants 1, 4 and 5 of FJOFC_TILE; not the double-buffered
+ * variant 0 or the 8-column variants 2 and 3).  A change of launch discards
+ * the captured graph (the next run captures again).                       */
 #define FJOFC_LAUNCH_LOCKSTEP 0
 #define FJOFC_LAUNCH_PERSISTENT 1
 int fjofc_batch_set_launch(fjofc_batch *b, int launch);
