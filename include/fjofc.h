@@ -46,7 +46,13 @@
  *                      8-row groups per wavefront); a comma-separated list
  *                      of "d:n_lo:n_hi:th:variant" forces it only for the
  *                      problems of that d with n_lo <= n <= n_hi (the
- *                      autotuner's per-bucket candidates);
+ *                      autotuner's per-bucket candidates).  Variants: 0 one
+ *                      wavefront, 4 columns per lane, 8-row groups,
+ *                      double-buffered loads; 1 the same, single-buffered;
+ *                      2 and 3 one wavefront, 8 columns per lane, 4- and
+ *                      8-row groups; 4 and 5 variant 1's wavefronts 4 x 1
+ *                      and 2 x 2 per tile (tile width 256, 256, 512, 512,
+ *                      256 and 512 columns);
  *  - FJOFC_OOS_OB      1..4 objects per out-of-sample workgroup (default 4);
  *  - FJOFC_OOS_SCALAR  any value: the out-of-sample stream uses 4-byte
  *                      loads even when n % 4 == 0;
